@@ -1,0 +1,226 @@
+/*
+ * hh.h - adaptive mixed-precision hybrid hierarchical (H_h) matrices on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Khan & Carson, "Hybrid hierarchical matrices with adaptive mixed
+ * precision storage". The library builds the H_h representation of a dense
+ * kernel matrix H_ij = f(|p_i - p_j|) (eq:kernel_mat) and applies it, or its
+ * transpose, to one or many vectors with hand-written gfx950 kernels.
+ *
+ * Conventions shared by every entry point
+ *   - Status codes: every function returns hh_status; on failure the
+ *     thread-local message of hh_last_error() says what was wrong. Inputs are
+ *     validated on the host before any device work is queued.
+ *   - Handles are opaque, own all their device memory and are immutable after
+ *     hh_build / hh_derive. Two threads may call hh_matvec on one handle only
+ *     on the same stream (the handle's workspace is shared).
+ *   - Vectors x and y of the products are DEVICE pointers, row-major
+ *     N x nrhs (a contiguous (N, nrhs) tensor), in the caller's point order.
+ *     y is overwritten (never accumulated into); x and y must not alias.
+ *   - Products are asynchronous on the given HIP stream (0 = null stream). A
+ *     device fault surfaces as HH_EHIP at the next synchronising call.
+ *   - The current HIP device at hh_build time is the device of the handle;
+ *     products must be called with that device current.
+ */
+#ifndef HH_H
+#define HH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hh_handle hh_handle;
+typedef struct hh_plan hh_plan;
+
+typedef enum {
+    HH_OK = 0,
+    HH_EINVAL = 1,     /* invalid argument (checked on the host, nothing queued) */
+    HH_ENOMEM = 2,     /* device or host allocation failed; nothing leaked       */
+    HH_EHIP = 3,       /* a HIP / rocBLAS / rocSOLVER call failed                 */
+    HH_ENOTSUP = 4,    /* valid but unsupported combination                       */
+    HH_EINTERNAL = 5   /* internal consistency check failed                       */
+} hh_status;
+
+/* Kernel functions of the paper's numerical section (Sec. 5) and the
+ * nonsymmetric double-layer kernel. Every entry is multiplied by `scale`.
+ *   HH_LOG          log r                       (singular: H_ii = 0)
+ *   HH_INV_R        1 / r                       (singular)
+ *   HH_INV_R2       1 / r^2                     (singular)
+ *   HH_GAUSS        exp(-r^2 / h^2)             (regular: H_ii = scale)
+ *   HH_MATERN       exp(-r / h)                 (regular)
+ *   HH_DOUBLE_LAYER n_j . (p_i - p_j) / r^3     (singular, nonsymmetric)
+ * For singular kernels the diagonal and the entries of coincident distinct
+ * points are 0 (the paper sets H_ii = 0 for singular f). */
+typedef enum {
+    HH_LOG = 1, HH_INV_R = 2, HH_INV_R2 = 3, HH_GAUSS = 4, HH_MATERN = 5,
+    HH_DOUBLE_LAYER = 6
+} hh_kernel_type;
+
+/* Storage formats of Table tab:precisions used for the low-rank factors. */
+enum { HH_FMT_FP64 = 0, HH_FMT_FP32 = 1, HH_FMT_FP16 = 2, HH_FMT_BF16 = 3 };
+/* Element type of x and y in the products. */
+enum { HH_IO_F64 = 0, HH_IO_F32 = 1 };
+
+/* Block kinds (Alg. 1). */
+enum {
+    HH_BLK_FAR = 0,        /* standard-admissible interaction list IL_s, levels 1..ell */
+    HH_BLK_NEAR = 1,       /* compressed finer neighbours N_s at the switching level    */
+    HH_BLK_WEAK = 2,       /* weak-admissible siblings IL_w, levels ell+1..L            */
+    HH_BLK_DIAG = 3,       /* dense leaf diagonal block                                  */
+    HH_BLK_DENSE_NEAR = 4  /* dense leaf neighbour (only when ell == L)                  */
+};
+
+typedef struct {
+    int type;                /* hh_kernel_type                                        */
+    double scale;            /* multiplies every entry (e.g. 1/(4 pi)); 0 means 1     */
+    double h;                /* length scale of HH_GAUSS / HH_MATERN; 0 means 1       */
+    const double* normals;   /* HOST, N x d row-major, HH_DOUBLE_LAYER only; copied   */
+} hh_kernel;
+
+typedef struct {
+    uint32_t precision_mask; /* bit f set = format f available to the rule;
+                                fp64 is always available. 0 means 0xF            */
+    int uniform_fp64;        /* 1: store every factor in fp64 (same tree, partition
+                                and ranks); the uniform-precision baseline        */
+    int io_dtype;            /* HH_IO_F64 (default) or HH_IO_F32 for x and y       */
+    uint64_t seed;           /* key of the randomized-compression sketches          */
+} hh_options;
+
+typedef struct {
+    int32_t n, d, L, ell;                 /* points, dimension, depth, switching level */
+    int32_t leaf_size, max_rank;
+    int64_t n_blocks_lowrank;             /* low-rank blocks with rank > 0             */
+    int64_t n_blocks_rank0;               /* admissible blocks compressed to rank 0    */
+    int64_t n_blocks_dense;               /* dense blocks (diagonal + dense neighbours) */
+    int64_t blocks_by_format[4];          /* low-rank blocks per HH_FMT_*              */
+    int64_t factor_bytes_by_format[4];    /* device bytes of U and V per format        */
+    int64_t dense_bytes;                  /* device bytes of dense blocks (fp64)       */
+    int64_t lowrank_entries;              /* sum_b k_b (m_b + n_b)                     */
+    int64_t dense_entries;                /* sum m n over dense blocks                 */
+    int64_t total_columns;                /* sum_b k_b                                  */
+    double storage_words;                 /* paper's bit-weighted storage, 64-bit words:
+                                             sum k (m + n) b / 64 + sum m n (Sec. 5.2)  */
+    double storage_words_fp64;            /* the same with every factor in fp64        */
+    double matvec_bytes;                  /* algorithmic HBM bytes of one nrhs = 1
+                                             product: factors + dense + x + y          */
+    double norm2_total;                   /* ||H~||_F^2 from Alg. 5                    */
+    double build_seconds;                 /* wall time of hh_build / hh_derive         */
+} hh_stats;
+
+typedef struct {                          /* one block, canonical order (level, i, j)  */
+    int32_t level, kind, rank, format;    /* kind HH_BLK_*, format HH_FMT_*           */
+    int64_t box_i, box_j;                 /* Morton indices of the two tree boxes     */
+    int64_t row_begin, row_end;           /* row range [begin, end) in tree order     */
+    int64_t col_begin, col_end;           /* column range in tree order               */
+    int32_t exp_u, exp_v;                 /* stored factor = value * 2^-exp            */
+    int32_t lowrank;                      /* 1 = U V^T factors, 0 = dense              */
+    double norm2;                         /* ||H~_b||^2 (truncated) or ||H_b||^2        */
+    double entry_norm2;                   /* ||H_b||_F^2 summed from the entries       */
+    double tail_prev, tail;               /* discarded tail at rank-1 and at rank      */
+} hh_block_info;
+
+/* ------------------------------------------------------------------ build */
+
+/* hh_build: H_h representation of the kernel matrix of `points`.
+ * Follows Alg. 1 (tree of Sec. 2.1, hybrid admissibility eq:hybrid_admiss,
+ * truncated-SVD compression with accuracy tol per admissible block, Def. of
+ * H_h(p, eps)), Alg. 5 (norms from singular values) and Alg. 3 (per-block
+ * storage precision: the largest unit roundoff u <= tol / (2^(d l / 2) xi_b)).
+ *   points        HOST, n x d row-major float64; copied.
+ *   n             number of points, >= 1.     d in {1, 2, 3}.
+ *   k             kernel description (not NULL).
+ *   tol           target accuracy eps, 2^-52 < tol < 1.
+ *   eta           admissibility parameter of eq:H_admiss, > 0.
+ *   switch_level  ell in [0, L]; -1 selects the paper's default L - 1. ell = L
+ *                 gives the H_s matrix, ell = 0 the HODLR matrix. L is the
+ *                 smallest L >= 0 with leaf_size * 2^(dL) >= n.
+ *   leaf_size     n_max >= 1.
+ *   opt           NULL for defaults.
+ *   out           receives the handle (set to NULL on failure).
+ * Runs synchronously on the current device; needs roughly
+ * 8 (sum_b k_b (m_b + n_b)) bytes of device memory beyond the result. */
+hh_status hh_build(const double* points, int64_t n, int d, const hh_kernel* k,
+                   double tol, double eta, int switch_level, int leaf_size,
+                   const hh_options* opt, hh_handle** out);
+
+/* hh_derive: a new handle with the same tree, partition and low-rank factors
+ * as `src`, re-stored under the precision rule of Alg. 3 with options `opt`.
+ * `src` must hold every low-rank factor in fp64 (built with uniform_fp64 = 1,
+ * or with precision_mask = fp64 only); HH_ENOTSUP otherwise, and when src
+ * has ell == L (its dense neighbours carry no factors). */
+hh_status hh_derive(const hh_handle* src, const hh_options* opt, hh_handle** out);
+
+/* -------------------------------------------------------------- products */
+
+/* hh_matvec: y = H^ x (Alg. 4): for every low-rank block y_I += U_b (V_b^T x_J),
+ * for every dense block y_I += H_IJ x_J. x, y DEVICE, n x nrhs row-major in the
+ * handle's io_dtype. Low-rank blocks stored in fp32 / fp64 and all dense blocks
+ * are applied in fp64 arithmetic; fp16 / bf16 blocks multiply and accumulate
+ * their inner products in fp32. Rows are accumulated in fp64, without atomics:
+ * results are bitwise reproducible run to run.  nrhs >= 1. */
+hh_status hh_matvec(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream);
+
+/* hh_matvec_t: y = H^^T x: y_J += V_b (U_b^T x_I), y_J += H_IJ^T x_I (dense
+ * blocks transposed inside the kernel). Same conventions as hh_matvec. */
+hh_status hh_matvec_t(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream);
+
+/* hh_matvec_batch: y_t = H_t^ x_t for `count` independent handles in one pass
+ * of the kernels (one launch per phase). Every handle must share io_dtype and
+ * the device; x[t], y[t] are DEVICE pointers sized for handle t. */
+hh_status hh_matvec_batch(const hh_handle* const* hs, int count, const void* const* x,
+                          void* const* y, int64_t nrhs, void* stream);
+
+/* hh_reserve: size the product workspace for up to max_nrhs right-hand sides
+ * now (products with larger nrhs allocate on first use, which is not allowed
+ * under HIP graph capture). */
+hh_status hh_reserve(hh_handle* h, int64_t max_nrhs);
+
+/* ------------------------------------------------------------ inspection */
+
+hh_status hh_get_stats(const hh_handle* h, hh_stats* out);
+/* Number of blocks (low-rank, rank-0 and dense), canonical order (level, i, j). */
+hh_status hh_block_count(const hh_handle* h, int64_t* count);
+hh_status hh_get_block(const hh_handle* h, int64_t index, hh_block_info* out);
+/* Stored factors of a low-rank block, decoded to float64 (value = stored * 2^exp):
+ * U HOST m x rank, V HOST n x rank, both column-major. For a dense block U
+ * receives the m x n block column-major and V is ignored. */
+hh_status hh_get_block_factors(const hh_handle* h, int64_t index, double* U, double* V);
+/* Tree order: perm[t] = caller index of the point at tree position t (HOST, n). */
+hh_status hh_get_perm(const hh_handle* h, int64_t* perm);
+int hh_io_dtype(const hh_handle* h);
+int64_t hh_size(const hh_handle* h);
+
+/* hh_free: release the handle and its device memory; NULL is a no-op. */
+void hh_free(hh_handle* h);
+
+/* ------------------------------------------------- host-only structure */
+
+/* hh_plan_*: the tree (Sec. 2.1) and block partition (Alg. 1) alone, computed
+ * on the host without a GPU; the same code hh_build uses. */
+hh_status hh_plan_create(const double* points, int64_t n, int d, double eta,
+                         int switch_level, int leaf_size, hh_plan** out);
+hh_status hh_plan_info(const hh_plan* p, int32_t* L, int32_t* ell, int64_t* n_blocks);
+/* Arrays of length n_blocks (any may be NULL): level, kind, Morton boxes i and
+ * j, tree-order row range [ib, ie) and column range [jb, je). */
+hh_status hh_plan_blocks(const hh_plan* p, int32_t* level, int32_t* kind, int64_t* box_i,
+                         int64_t* box_j, int64_t* ib, int64_t* ie, int64_t* jb, int64_t* je);
+hh_status hh_plan_perm(const hh_plan* p, int64_t* perm);
+void hh_plan_free(hh_plan* p);
+
+/* hh_quantize: the library's storage rounding on the host: out[i] = round(in[i]
+ * 2^-e) 2^e with round-to-nearest-even straight from float64 to `format`
+ * (HH_FMT_*), gradual underflow kept. This is the arithmetic hh_build applies
+ * to every factor (e = 0 for fp64 / fp32; the build picks e per factor so that
+ * the largest entry lands in [2^14, 2^15) for fp16 and in [1, 2) for bf16). */
+hh_status hh_quantize(const double* in, int64_t n, int format, int e, double* out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* hh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HH_H */

@@ -527,6 +527,20 @@ def scale_exponent(F: np.ndarray, fmt: int) -> int:
     return top - 14 if fmt == FMT_FP16 else top
 
 
+def round_to(G: np.ndarray, fmt: int) -> np.ndarray:
+    """Nearest value of format `fmt` (ties to even), straight from float64."""
+    G = np.asarray(G, dtype=np.float64)
+    if fmt == FMT_FP64:
+        return G.copy()
+    if fmt == FMT_FP32:
+        with np.errstate(over="ignore"):
+            return G.astype(np.float32).astype(np.float64)
+    if fmt == FMT_FP16:
+        with np.errstate(over="ignore"):
+            return G.astype(np.float16).astype(np.float64)
+    return round_bf16(G)
+
+
 def quantize(F: np.ndarray, fmt: int) -> tuple:
     """(stored values as float64, stored raw array, exponent e); value = stored 2^e."""
     e = scale_exponent(F, fmt)

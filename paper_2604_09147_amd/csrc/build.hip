@@ -1,0 +1,905 @@
+// Construction of an H_h handle on the GPU: Alg. 1 (compression of every
+// admissible block with target accuracy eps), Alg. 5 (norms from singular
+// values) and Alg. 3 (per-block storage precision), followed by the layout of
+// the product kernels' tasks.
+//
+// Compression: blocks with min(m, n) <= 512 use a full SVD; larger blocks use a
+// randomized range finder (Rademacher sketch keyed by (seed, block, round), one
+// power iteration, width 32 doubling while rank + 16 > width) whose truncation
+// error ||H - Q Q^T H||_F^2 is summed directly, so that every block satisfies
+// ||H_b - U_b V_b^T||_F <= eps ||H_b||_F (Def. of H_h(p, eps)). Batches of
+// similar blocks run through rocBLAS / rocSOLVER strided-batched calls after
+// zero padding to the batch maximum (zero rows and columns change neither the
+// singular values nor the factors' real rows).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "handle.h"
+
+namespace hh {
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            fail(HH_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+#define RBCHK(x)                                                                           \
+    do {                                                                                   \
+        rocblas_status s_ = (x);                                                           \
+        if (s_ != rocblas_status_success)                                                  \
+            fail(s_ == rocblas_status_memory_error ? HH_ENOMEM : HH_EHIP,                  \
+                 std::string(#x) + ": rocblas status " + std::to_string((int)s_));         \
+    } while (0)
+
+constexpr int EXACT_SVD_MAX = 512;
+constexpr int SKETCH_START = 32;
+constexpr int OVERSAMPLE = 16;
+constexpr int64_t SUM_CHUNK = 65536;
+constexpr int64_t DOT_TASK_ELEMS = 65536;
+
+void* DevMem::alloc(size_t bytes, bool zero) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(HH_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    if (zero) {
+        e = hipMemset(p, 0, bytes);
+        if (e != hipSuccess) fail(HH_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
+    }
+    return p;
+}
+
+void DevMem::release(void* p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+        (void)hipFree(p);
+        ptrs.erase(it);
+    }
+}
+
+void DevMem::free_all() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+}
+
+static size_t fmt_size(int fmt) { return fmt == HH_FMT_FP64 ? 8 : fmt == HH_FMT_FP32 ? 4 : 2; }
+static const double UNIT[4] = {0x1p-53, 0x1p-24, 0x1p-11, 0x1p-8};
+static const int BITS[4] = {64, 32, 16, 16};
+
+template <class T>
+static T* upload(DevMem& m, const std::vector<T>& v) {
+    T* d = static_cast<T*>(m.alloc(v.size() * sizeof(T) + 16, false));
+    if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+// Bump allocator over one scratch buffer.
+struct Carver {
+    char* base;
+    size_t cap;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        size_t b = (count * sizeof(T) + 255) & ~(size_t)255;
+        if (off + b > cap) fail(HH_EINTERNAL, "construction scratch overflow");
+        T* p = reinterpret_cast<T*>(base + off);
+        off += b;
+        return p;
+    }
+};
+
+struct Builder {
+    hh_handle* h;
+    rocblas_handle rb = nullptr;
+    hipStream_t st = 0;
+    DevMem scratch_mem;
+    char* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    double eps2;
+    std::vector<double*> store_chunks;   // fp64 factors (freed after packing unless kept)
+    DevMem store;
+
+    explicit Builder(hh_handle* hh) : h(hh), eps2(hh->tol * hh->tol) {}
+    ~Builder() {
+        if (rb) rocblas_destroy_handle(rb);
+    }
+
+    template <class T>
+    T* meta(const std::vector<T>& v, Carver& cv) {
+        T* d = cv.take<T>(v.size() + 1);
+        if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return d;
+    }
+
+    void init() {
+        RBCHK(rocblas_create_handle(&rb));
+        RBCHK(rocblas_set_stream(rb, st));
+        size_t freeb = 0, totalb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totalb));
+        size_t want = freeb / 5;
+        if (want > ((size_t)16 << 30)) want = (size_t)16 << 30;
+        if (want < ((size_t)64 << 20)) want = (size_t)64 << 20;
+        scratch_bytes = want;
+        scratch = static_cast<char*>(scratch_mem.alloc(scratch_bytes, false));
+    }
+
+    // Allocate the fp64 store of a batch and record each block's factor pointers.
+    double* store_for(const std::vector<int64_t>& idx, const std::vector<int>& ranks) {
+        int64_t total = 0;
+        for (size_t b = 0; b < idx.size(); ++b) {
+            const BlockRec& r = h->blocks[idx[b]];
+            total += (int64_t)ranks[b] * (r.PI + r.PJ);
+        }
+        double* s = static_cast<double*>(store.alloc((size_t)total * 8 + 256, true));
+        int64_t off = 0;
+        for (size_t b = 0; b < idx.size(); ++b) {
+            BlockRec& r = h->blocks[idx[b]];
+            r.u_ptr = s + off;
+            off += (int64_t)ranks[b] * r.PI;
+            r.v_ptr = s + off;
+            off += (int64_t)ranks[b] * r.PJ;
+        }
+        return s;
+    }
+
+    void record_rank(int64_t bi, const RankItem& it) {
+        BlockRec& r = h->blocks[bi];
+        r.rank = it.rank;
+        r.entry2 = it.norm2;
+        r.nb2 = it.trunc2;
+        r.tail = it.tail;
+        r.tail_prev = it.tail_prev;
+        r.fmt = HH_FMT_FP64;
+    }
+
+    void exact_batch(const std::vector<int64_t>& idx) {
+        const int B = (int)idx.size();
+        int64_t M = 0, N = 0;
+        for (int64_t i : idx) {
+            M = std::max<int64_t>(M, h->blocks[i].b.ie - h->blocks[i].b.ib);
+            N = std::max<int64_t>(N, h->blocks[i].b.je - h->blocks[i].b.jb);
+        }
+        const int64_t p = std::min(M, N);
+        const int64_t nch = (M * N + SUM_CHUNK - 1) / SUM_CHUNK;
+        Carver cv{scratch, scratch_bytes};
+        double* A = cv.take<double>((size_t)B * M * N);
+        double* U = cv.take<double>((size_t)B * M * p);
+        double* Vt = cv.take<double>((size_t)B * p * N);
+        double* S = cv.take<double>((size_t)B * p);
+        double* E = cv.take<double>((size_t)B * p);
+        double* nrm = cv.take<double>(B);
+        double* part = cv.take<double>((size_t)B * nch);
+        rocblas_int* info = cv.take<rocblas_int>(B);
+        std::vector<GenItem> gi(B);
+        std::vector<SumItem> si(B);
+        std::vector<RankItem> ri(B);
+        for (int b = 0; b < B; ++b) {
+            const Blk& k = h->blocks[idx[b]].b;
+            gi[b] = GenItem{k.ib, k.jb, k.ie - k.ib, k.je - k.jb, A + (int64_t)b * M * N, M, 0, 0};
+            si[b] = SumItem{A + (int64_t)b * M * N, M * N};
+            RankItem r{};
+            r.sigma = S + (int64_t)b * p;
+            r.norm2p = nrm + b;
+            r.extrap = nullptr;
+            r.p = (int)p;
+            r.sketch = 0;
+            r.pmin = (int)std::min(k.ie - k.ib, k.je - k.jb);
+            ri[b] = r;
+        }
+        launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, meta(gi, cv), B, M, N, M * N, st);
+        launch_sumsq(meta(si, cv), B, M * N, part, SUM_CHUNK, nrm, st);
+        RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_singular,
+                                               (rocblas_int)M, (rocblas_int)N, A, (rocblas_int)M,
+                                               M * N, S, p, U, (rocblas_int)M, M * p, Vt,
+                                               (rocblas_int)p, p * N, E, p, rocblas_outofplace,
+                                               info, B));
+        RankItem* dri = meta(ri, cv);
+        launch_rank(dri, B, eps2, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(ri.data(), dri, B * sizeof(RankItem), hipMemcpyDeviceToHost));
+        check_info(info, B);
+        std::vector<int> ranks(B);
+        for (int b = 0; b < B; ++b) {
+            record_rank(idx[b], ri[b]);
+            ranks[b] = ri[b].rank;
+        }
+        store_for(idx, ranks);
+        std::vector<FinItem> fi;
+        for (int b = 0; b < B; ++b) {
+            const BlockRec& r = h->blocks[idx[b]];
+            if (!ranks[b]) continue;
+            FinItem f{};
+            f.U = U + (int64_t)b * M * p;
+            f.Vt = Vt + (int64_t)b * p * N;
+            f.sigma = S + (int64_t)b * p;
+            f.Uout = (double*)r.u_ptr;
+            f.Vout = (double*)r.v_ptr;
+            f.ib = r.b.ib;
+            f.jb = r.b.jb;
+            f.ldu = M;
+            f.ldv = p;
+            f.PI = r.PI;
+            f.PJ = r.PJ;
+            f.m = (int)(r.b.ie - r.b.ib);
+            f.n = (int)(r.b.je - r.b.jb);
+            f.k = ranks[b];
+            fi.push_back(f);
+        }
+        if (!fi.empty()) launch_finalize(meta(fi, cv), (int)fi.size(), h->d_tpad, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipDeviceSynchronize());
+    }
+
+    void check_info(const rocblas_int* dinfo, int B) {
+        std::vector<rocblas_int> hi(B);
+        HIPCHK(hipMemcpy(hi.data(), dinfo, B * sizeof(rocblas_int), hipMemcpyDeviceToHost));
+        for (int b = 0; b < B; ++b)
+            if (hi[b] != 0) fail(HH_EINTERNAL, "SVD did not converge (info " + std::to_string(hi[b]) + ")");
+    }
+
+    void orth(double* Y, int64_t rows, int64_t s, double* Q, double* S2, double* E2, double* dummy,
+              rocblas_int* info, int B) {
+        RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_none,
+                                               (rocblas_int)rows, (rocblas_int)s, Y,
+                                               (rocblas_int)rows, rows * s, S2, s, Q,
+                                               (rocblas_int)rows, rows * s, dummy, 1, 1, E2, s,
+                                               rocblas_outofplace, info, B));
+    }
+
+    // One randomized round for a batch sharing sketch width s; returns the
+    // blocks that need a wider sketch.
+    std::vector<int64_t> random_batch(const std::vector<int64_t>& idx, int s, int round) {
+        const int B = (int)idx.size();
+        int64_t M = 0, N = 0;
+        for (int64_t i : idx) {
+            M = std::max<int64_t>(M, h->blocks[i].b.ie - h->blocks[i].b.ib);
+            N = std::max<int64_t>(N, h->blocks[i].b.je - h->blocks[i].b.jb);
+        }
+        const int64_t nch = (M * N + SUM_CHUNK - 1) / SUM_CHUNK;
+        Carver cv{scratch, scratch_bytes};
+        double* H = cv.take<double>((size_t)B * M * N);
+        double* Om = cv.take<double>((size_t)B * N * s);
+        double* Y = cv.take<double>((size_t)B * M * s);
+        double* Q = cv.take<double>((size_t)B * M * s);
+        double* Z = cv.take<double>((size_t)B * N * s);
+        double* Q2 = cv.take<double>((size_t)B * N * s);
+        double* Bm = cv.take<double>((size_t)B * s * N);
+        double* Ub = cv.take<double>((size_t)B * s * s);
+        double* Vt = cv.take<double>((size_t)B * s * N);
+        double* S = cv.take<double>((size_t)B * s);
+        double* E = cv.take<double>((size_t)B * s);
+        double* S2 = cv.take<double>((size_t)B * s);
+        double* E2 = cv.take<double>((size_t)B * s);
+        double* nrm = cv.take<double>(B);
+        double* e2 = cv.take<double>(B);
+        double* part = cv.take<double>((size_t)B * nch);
+        double* dummy = cv.take<double>(16);
+        rocblas_int* info = cv.take<rocblas_int>(B);
+        std::vector<GenItem> gi(B);
+        std::vector<SumItem> si(B);
+        std::vector<SketchItem> ski(B);
+        for (int b = 0; b < B; ++b) {
+            const Blk& k = h->blocks[idx[b]].b;
+            gi[b] = GenItem{k.ib, k.jb, k.ie - k.ib, k.je - k.jb, H + (int64_t)b * M * N, M, 0, 0};
+            si[b] = SumItem{H + (int64_t)b * M * N, M * N};
+            ski[b] = SketchItem{Om + (int64_t)b * N * s, k.je - k.jb, idx[b], round, 0};
+        }
+        SumItem* dsi = meta(si, cv);
+        launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, meta(gi, cv), B, M, N, M * N, st);
+        launch_sumsq(dsi, B, M * N, part, SUM_CHUNK, nrm, st);
+        launch_sketch(meta(ski, cv), B, N, s, h->opt.seed, st);
+        const double one = 1.0, zero = 0.0, mone = -1.0;
+        const rocblas_operation NT = rocblas_operation_none, TR = rocblas_operation_transpose;
+        const rocblas_int iM = (rocblas_int)M, iN = (rocblas_int)N, is = s;
+        // range finder with one power iteration
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, iN, &one, H, iM, M * N, Om, iN,
+                                            N * s, &zero, Y, iM, M * s, B));
+        orth(Y, M, s, Q, S2, E2, dummy, info, B);
+        RBCHK(rocblas_dgemm_strided_batched(rb, TR, NT, iN, is, iM, &one, H, iM, M * N, Q, iM,
+                                            M * s, &zero, Z, iN, N * s, B));
+        orth(Z, N, s, Q2, S2, E2, dummy, info, B);
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, iN, &one, H, iM, M * N, Q2, iN,
+                                            N * s, &zero, Y, iM, M * s, B));
+        orth(Y, M, s, Q, S2, E2, dummy, info, B);
+        // B = Q^T H, then H <- H - Q B and its Frobenius norm (the discarded part)
+        RBCHK(rocblas_dgemm_strided_batched(rb, TR, NT, is, iN, iM, &one, Q, iM, M * s, H, iM,
+                                            M * N, &zero, Bm, is, s * N, B));
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, iN, is, &mone, Q, iM, M * s, Bm, is,
+                                            s * N, &one, H, iM, M * N, B));
+        launch_sumsq(dsi, B, M * N, part, SUM_CHUNK, e2, st);
+        RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_singular,
+                                               is, iN, Bm, is, s * N, S, s, Ub, is, s * s, Vt, is,
+                                               s * N, E, s, rocblas_outofplace, info, B));
+        std::vector<RankItem> ri(B);
+        for (int b = 0; b < B; ++b) {
+            const Blk& k = h->blocks[idx[b]].b;
+            RankItem r{};
+            r.sigma = S + (int64_t)b * s;
+            r.norm2p = nrm + b;
+            r.extrap = e2 + b;
+            r.p = s;
+            r.sketch = s;
+            r.pmin = (int)std::min(k.ie - k.ib, k.je - k.jb);
+            r.oversample = OVERSAMPLE;
+            ri[b] = r;
+        }
+        RankItem* dri = meta(ri, cv);
+        launch_rank(dri, B, eps2, st);
+        // U = Q Ub for every item (only accepted ones are kept)
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, is, &one, Q, iM, M * s, Ub, is,
+                                            s * s, &zero, Y, iM, M * s, B));
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(ri.data(), dri, B * sizeof(RankItem), hipMemcpyDeviceToHost));
+        check_info(info, B);
+        std::vector<int64_t> acc_idx, retry;
+        std::vector<int> acc_rank, acc_pos;
+        for (int b = 0; b < B; ++b) {
+            if (ri[b].accept) {
+                record_rank(idx[b], ri[b]);
+                acc_idx.push_back(idx[b]);
+                acc_rank.push_back(ri[b].rank);
+                acc_pos.push_back(b);
+            } else {
+                retry.push_back(idx[b]);
+            }
+        }
+        if (!acc_idx.empty()) {
+            store_for(acc_idx, acc_rank);
+            std::vector<FinItem> fi;
+            for (size_t a = 0; a < acc_idx.size(); ++a) {
+                const BlockRec& r = h->blocks[acc_idx[a]];
+                const int b = acc_pos[a];
+                if (!acc_rank[a]) continue;
+                FinItem f{};
+                f.U = Y + (int64_t)b * M * s;
+                f.Vt = Vt + (int64_t)b * s * N;
+                f.sigma = S + (int64_t)b * s;
+                f.Uout = (double*)r.u_ptr;
+                f.Vout = (double*)r.v_ptr;
+                f.ib = r.b.ib;
+                f.jb = r.b.jb;
+                f.ldu = M;
+                f.ldv = s;
+                f.PI = r.PI;
+                f.PJ = r.PJ;
+                f.m = (int)(r.b.ie - r.b.ib);
+                f.n = (int)(r.b.je - r.b.jb);
+                f.k = acc_rank[a];
+                fi.push_back(f);
+            }
+            if (!fi.empty()) launch_finalize(meta(fi, cv), (int)fi.size(), h->d_tpad, st);
+            HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipDeviceSynchronize());
+        return retry;
+    }
+
+    size_t exact_item_bytes(int64_t M, int64_t N) const {
+        int64_t p = std::min(M, N);
+        return 8 * (size_t)(M * N + M * p + p * N + 2 * p + 2 + (M * N) / SUM_CHUNK + 1) + 1024;
+    }
+    size_t random_item_bytes(int64_t M, int64_t N, int64_t s) const {
+        return 8 * (size_t)(M * N + 2 * N * s + 2 * M * s + 2 * N * s + s * s + 2 * s * N +
+                            4 * s + 3 + (M * N) / SUM_CHUNK + 1) + 2048;
+    }
+
+    // Greedy batches of blocks sorted by size, bounded by the scratch budget.
+    template <class F, class G>
+    void batched(std::vector<int64_t> list, F item_bytes, G run) {
+        std::sort(list.begin(), list.end(), [&](int64_t a, int64_t b) {
+            const Blk &x = h->blocks[a].b, &y = h->blocks[b].b;
+            int64_t xm = x.ie - x.ib, ym = y.ie - y.ib, xn = x.je - x.jb, yn = y.je - y.jb;
+            if (xm != ym) return xm > ym;
+            if (xn != yn) return xn > yn;
+            return a < b;
+        });
+        size_t i = 0;
+        const size_t budget = scratch_bytes * 9 / 10;
+        while (i < list.size()) {
+            std::vector<int64_t> batch;
+            int64_t M = 0, N = 0;
+            while (i < list.size() && batch.size() < 4096) {
+                const Blk& k = h->blocks[list[i]].b;
+                int64_t M2 = std::max<int64_t>(M, k.ie - k.ib), N2 = std::max<int64_t>(N, k.je - k.jb);
+                if (!batch.empty() && item_bytes(M2, N2) * (batch.size() + 1) > budget) break;
+                if (batch.empty() && item_bytes(M2, N2) > budget)
+                    fail(HH_ENOMEM, "a single block does not fit the construction scratch");
+                M = M2;
+                N = N2;
+                batch.push_back(list[i++]);
+            }
+            run(batch);
+        }
+    }
+
+    void compress(const std::vector<int64_t>& cand) {
+        std::vector<int64_t> exact, rnd;
+        for (int64_t i : cand) {
+            const Blk& k = h->blocks[i].b;
+            (std::min(k.ie - k.ib, k.je - k.jb) <= EXACT_SVD_MAX ? exact : rnd).push_back(i);
+        }
+        batched(exact, [&](int64_t M, int64_t N) { return exact_item_bytes(M, N); },
+                [&](const std::vector<int64_t>& b) { exact_batch(b); });
+        // randomized: groups keyed by sketch width, widening on demand
+        std::map<int, std::vector<int64_t>> queue;
+        std::map<int64_t, int> rounds;
+        for (int64_t i : rnd) {
+            queue[SKETCH_START].push_back(i);
+            rounds[i] = 0;
+        }
+        while (!queue.empty()) {
+            auto it = queue.begin();
+            const int s = it->first;
+            std::vector<int64_t> list = std::move(it->second);
+            queue.erase(it);
+            // items with different round counters cannot share a launch (they do
+            // share s, so rounds coincide unless s was clipped to min(m, n))
+            std::map<int, std::vector<int64_t>> by_round;
+            for (int64_t i : list) by_round[rounds[i]].push_back(i);
+            for (auto& kv : by_round) {
+                const int round = kv.first;
+                batched(kv.second,
+                        [&](int64_t M, int64_t N) { return random_item_bytes(M, N, s); },
+                        [&](const std::vector<int64_t>& b) {
+                            for (int64_t r : random_batch(b, s, round)) {
+                                const Blk& k = h->blocks[r].b;
+                                int pmin = (int)std::min(k.ie - k.ib, k.je - k.jb);
+                                int s2 = std::min(2 * s, pmin);
+                                if (s2 <= s) fail(HH_EINTERNAL, "sketch cannot widen");
+                                rounds[r] = round + 1;
+                                queue[s2].push_back(r);
+                            }
+                        });
+            }
+        }
+    }
+
+    // Dense blocks generated in place (padded-row layout) and their norms.
+    void dense(const std::vector<int64_t>& list) {
+        if (list.empty()) return;
+        int64_t total = 0;
+        for (int64_t i : list) {
+            const BlockRec& r = h->blocks[i];
+            total += r.PI * (r.b.je - r.b.jb);
+        }
+        double* D = static_cast<double*>(h->mem.alloc((size_t)total * 8 + 256, true));
+        int64_t off = 0;
+        std::vector<GenItem> gi;
+        std::vector<SumItem> si;
+        int64_t maxmn = 0, maxcount = 0;
+        for (int64_t i : list) {
+            BlockRec& r = h->blocks[i];
+            const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
+            r.d_ptr = D + off;
+            r.lowrank = false;
+            r.rank = 0;
+            r.fmt = HH_FMT_FP64;
+            gi.push_back(GenItem{r.b.ib, r.b.jb, m, n, D + off, r.PI, 1, 0});
+            si.push_back(SumItem{D + off, r.PI * n});
+            maxmn = std::max(maxmn, m * n);
+            maxcount = std::max(maxcount, r.PI * n);
+            off += r.PI * n;
+        }
+        for (size_t a = 0; a < gi.size(); a += 32768) {
+            size_t e = std::min(gi.size(), a + 32768);
+            std::vector<GenItem> g(gi.begin() + a, gi.begin() + e);
+            std::vector<SumItem> s(si.begin() + a, si.begin() + e);
+            Carver cv{scratch, scratch_bytes};
+            const int B = (int)g.size();
+            const int64_t nch = (maxcount + SUM_CHUNK - 1) / SUM_CHUNK;
+            double* part = cv.take<double>((size_t)B * nch);
+            double* nrm = cv.take<double>(B);
+            launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, meta(g, cv), B, 0, 0, maxmn, st);
+            launch_sumsq(meta(s, cv), B, maxcount, part, SUM_CHUNK, nrm, st);
+            std::vector<double> hn(B);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpy(hn.data(), nrm, B * sizeof(double), hipMemcpyDeviceToHost));
+            for (int b = 0; b < B; ++b) {
+                BlockRec& r = h->blocks[list[a + b]];
+                r.entry2 = hn[b];
+                r.nb2 = hn[b];
+            }
+        }
+    }
+
+    // Alg. 3 storage: round every low-rank factor into its format's arena.
+    void pack() {
+        int64_t need[4] = {0, 0, 0, 0};
+        std::vector<int64_t> lr;
+        for (size_t i = 0; i < h->blocks.size(); ++i) {
+            const BlockRec& r = h->blocks[i];
+            if (r.lowrank && r.rank > 0) {
+                lr.push_back((int64_t)i);
+                need[r.fmt] += (int64_t)r.rank * (r.PI + r.PJ);
+            }
+        }
+        bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0;
+        h->all_fp64 = all64;
+        if (all64) return;   // the fp64 store already is the arena
+        // exponents of the scaled formats
+        std::vector<double> mx(2 * lr.size(), 0.0);
+        {
+            std::vector<SumItem> items;
+            for (int64_t i : lr) {
+                const BlockRec& r = h->blocks[i];
+                items.push_back(SumItem{(const double*)r.u_ptr, (int64_t)r.rank * r.PI});
+                items.push_back(SumItem{(const double*)r.v_ptr, (int64_t)r.rank * r.PJ});
+            }
+            for (size_t a = 0; a < items.size(); a += 65536) {
+                size_t e = std::min(items.size(), a + 65536);
+                std::vector<SumItem> part(items.begin() + a, items.begin() + e);
+                Carver cv{scratch, scratch_bytes};
+                double* out = cv.take<double>(part.size());
+                launch_maxabs(meta(part, cv), (int)part.size(), out, st);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpy(mx.data() + a, out, part.size() * 8, hipMemcpyDeviceToHost));
+            }
+        }
+        char* arena[4] = {nullptr, nullptr, nullptr, nullptr};
+        for (int f = 0; f < 4; ++f)
+            if (need[f]) arena[f] = static_cast<char*>(h->mem.alloc((size_t)need[f] * fmt_size(f) + 256, false));
+        int64_t off[4] = {0, 0, 0, 0};
+        std::vector<PackItem> items;
+        int64_t maxcount = 0;
+        for (size_t a = 0; a < lr.size(); ++a) {
+            BlockRec& r = h->blocks[lr[a]];
+            auto expo = [&](double m) {
+                if (r.fmt == HH_FMT_FP64 || r.fmt == HH_FMT_FP32 || m == 0.0) return 0;
+                int q;
+                std::frexp(m, &q);
+                return r.fmt == HH_FMT_FP16 ? q - 1 - 14 : q - 1;
+            };
+            r.eU = expo(mx[2 * a]);
+            r.eV = expo(mx[2 * a + 1]);
+            const size_t es = fmt_size(r.fmt);
+            char* up = arena[r.fmt] + off[r.fmt] * es;
+            off[r.fmt] += (int64_t)r.rank * r.PI;
+            char* vp = arena[r.fmt] + off[r.fmt] * es;
+            off[r.fmt] += (int64_t)r.rank * r.PJ;
+            items.push_back(PackItem{(const double*)r.u_ptr, up, (int64_t)r.rank * r.PI, r.fmt, r.eU});
+            items.push_back(PackItem{(const double*)r.v_ptr, vp, (int64_t)r.rank * r.PJ, r.fmt, r.eV});
+            maxcount = std::max(maxcount, std::max((int64_t)r.rank * r.PI, (int64_t)r.rank * r.PJ));
+            r.u_ptr = up;
+            r.v_ptr = vp;
+        }
+        for (size_t a = 0; a < items.size(); a += 32768) {
+            size_t e = std::min(items.size(), a + 32768);
+            std::vector<PackItem> part(items.begin() + a, items.begin() + e);
+            Carver cv{scratch, scratch_bytes};
+            launch_pack(meta(part, cv), (int)part.size(), maxcount, st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipDeviceSynchronize());
+        }
+        store.free_all();
+    }
+};
+
+// ----------------------------------------------------------- layout + tasks
+static void layout(hh_handle* h) {
+    const Plan& P = h->plan;
+    const int L = P.L, d = P.d;
+    const auto& rl = P.ranges[L];
+    const int64_t nleaf = (int64_t)1 << (d * L);
+    h->leaf_poff.assign(nleaf, 0);
+    h->leaf_psz.assign(nleaf, 0);
+    h->tpad.assign(P.n, 0);
+    int64_t off = 0;
+    for (int64_t b = 0; b < nleaf; ++b) {
+        int64_t cnt = rl[2 * b + 1] - rl[2 * b];
+        h->leaf_poff[b] = off;
+        h->leaf_psz[b] = (cnt + ROW_PAD - 1) / ROW_PAD * ROW_PAD;
+        for (int64_t t = rl[2 * b]; t < rl[2 * b + 1]; ++t) h->tpad[t] = off + (t - rl[2 * b]);
+        off += h->leaf_psz[b];
+    }
+    h->np = off;
+    auto cluster = [&](int level, int64_t box, int64_t& start, int64_t& len) {
+        int sh = d * (L - level);
+        int64_t first = box << sh, last = ((box + 1) << sh) - 1;
+        start = h->leaf_poff[first];
+        len = h->leaf_poff[last] + h->leaf_psz[last] - start;
+    };
+    h->blocks.resize(P.blocks.size());
+    for (size_t i = 0; i < P.blocks.size(); ++i) {
+        BlockRec& r = h->blocks[i];
+        r = BlockRec{};
+        r.b = P.blocks[i];
+        cluster(r.b.level, r.b.bi, r.pI, r.PI);
+        cluster(r.b.level, r.b.bj, r.pJ, r.PJ);
+    }
+}
+
+static void build_tasks(hh_handle* h) {
+    const Plan& P = h->plan;
+    const int L = P.L, d = P.d;
+    int64_t col = 0;
+    for (auto& r : h->blocks)
+        if (r.lowrank && r.rank > 0) {
+            r.col = col;
+            col += r.rank;
+        }
+    h->ncols = col;
+    TaskSet& F = h->fwd;
+    TaskSet& T = h->bwd;
+    for (const auto& r : h->blocks) {
+        if (!(r.lowrank && r.rank > 0)) continue;
+        const size_t es = fmt_size(r.fmt);
+        for (int pass = 0; pass < 2; ++pass) {
+            const int64_t Pl = pass == 0 ? r.PJ : r.PI;
+            const char* base = static_cast<const char*>(pass == 0 ? r.v_ptr : r.u_ptr);
+            int64_t cpt = std::max<int64_t>(1, std::min<int64_t>(r.rank, DOT_TASK_ELEMS / std::max<int64_t>(Pl, 1)));
+            for (int64_t c0 = 0; c0 < r.rank; c0 += cpt) {
+                DotTask t{};
+                t.col0 = base + (size_t)(c0 * Pl) * es;
+                t.xoff = pass == 0 ? r.pJ : r.pI;
+                t.toff = r.col + c0;
+                t.P = (int32_t)Pl;
+                t.ncols = (int32_t)std::min<int64_t>(cpt, r.rank - c0);
+                t.fmt = r.fmt;
+                t.hid = 0;
+                (pass == 0 ? F : T).dot.push_back(t);
+            }
+        }
+    }
+    // blocks by (level, row box) and (level, column box)
+    std::map<std::pair<int, int64_t>, std::vector<int64_t>> by_row, by_col;
+    for (size_t i = 0; i < h->blocks.size(); ++i) {
+        const Blk& b = h->blocks[i].b;
+        by_row[{b.level, b.bi}].push_back((int64_t)i);
+        by_col[{b.level, b.bj}].push_back((int64_t)i);
+    }
+    const int64_t nleaf = (int64_t)1 << (d * L);
+    for (int64_t lf = 0; lf < nleaf; ++lf) {
+        if (h->leaf_psz[lf] == 0) continue;
+        for (int dir = 0; dir < 2; ++dir) {
+            TaskSet& S = dir == 0 ? F : T;
+            LeafTask lt{};
+            lt.poff = h->leaf_poff[lf];
+            lt.P = (int32_t)h->leaf_psz[lf];
+            lt.run_begin = (int32_t)S.runs.size();
+            lt.drun_begin = (int32_t)S.druns.size();
+            for (int l = 0; l <= L; ++l) {
+                int64_t anc = lf >> (d * (L - l));
+                auto& mp = dir == 0 ? by_row : by_col;
+                auto it = mp.find({l, anc});
+                if (it == mp.end()) continue;
+                for (int64_t bi : it->second) {
+                    const BlockRec& r = h->blocks[bi];
+                    if (r.lowrank) {
+                        if (r.rank == 0) continue;
+                        const size_t es = fmt_size(r.fmt);
+                        Run rn{};
+                        const int64_t rowoff = dir == 0 ? lt.poff - r.pI : lt.poff - r.pJ;
+                        rn.base = static_cast<const char*>(dir == 0 ? r.u_ptr : r.v_ptr) + (size_t)rowoff * es;
+                        rn.stride = dir == 0 ? r.PI : r.PJ;
+                        rn.toff = r.col;
+                        rn.scale = std::ldexp(1.0, r.eU + r.eV);
+                        rn.ncols = r.rank;
+                        rn.fmt = r.fmt;
+                        rn.from_x = 0;
+                        S.runs.push_back(rn);
+                    } else if (dir == 0) {
+                        Run rn{};
+                        rn.base = r.d_ptr;
+                        rn.stride = r.PI;
+                        rn.toff = r.pJ;
+                        rn.scale = 1.0;
+                        rn.ncols = (int32_t)(r.b.je - r.b.jb);
+                        rn.fmt = HH_FMT_FP64;
+                        rn.from_x = 1;
+                        S.runs.push_back(rn);
+                    } else {
+                        DotRun dr{};
+                        dr.base = r.d_ptr;
+                        dr.xoff = r.pI;
+                        dr.P = (int32_t)r.PI;
+                        dr.ncols = (int32_t)(r.b.je - r.b.jb);
+                        S.druns.push_back(dr);
+                    }
+                }
+            }
+            lt.run_end = (int32_t)S.runs.size();
+            lt.drun_end = (int32_t)S.druns.size();
+            S.leaf.push_back(lt);
+        }
+    }
+    for (TaskSet* S : {&F, &T}) {
+        S->d_dot = upload(h->mem, S->dot);
+        S->d_leaf = upload(h->mem, S->leaf);
+        S->d_runs = upload(h->mem, S->runs);
+        S->d_druns = upload(h->mem, S->druns);
+    }
+}
+
+static bool choose_lowrank_format(const BlockRec& r, double total2, int d, double eps,
+                                  uint32_t mask, int& fmt) {
+    const double rhs = (eps * eps) * total2;
+    const int order[3] = {HH_FMT_BF16, HH_FMT_FP16, HH_FMT_FP32};
+    for (int f : order) {
+        if (!(mask & (1u << f))) continue;
+        const double u = UNIT[f];
+        if (((u * u) * std::ldexp(1.0, d * r.b.level)) * r.nb2 <= rhs) {
+            fmt = f;
+            return true;
+        }
+    }
+    fmt = HH_FMT_FP64;
+    return true;
+}
+
+static void fill_stats(hh_handle* h, double seconds) {
+    hh_stats& s = h->stats;
+    s = hh_stats{};
+    s.n = (int32_t)h->plan.n;
+    s.d = h->plan.d;
+    s.L = h->plan.L;
+    s.ell = h->plan.ell;
+    s.leaf_size = h->plan.leaf_size;
+    double words = 0, words64 = 0, bytes = 0;
+    for (const auto& r : h->blocks) {
+        const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
+        if (r.lowrank) {
+            if (r.rank == 0) {
+                s.n_blocks_rank0++;
+                continue;
+            }
+            s.n_blocks_lowrank++;
+            s.blocks_by_format[r.fmt]++;
+            s.factor_bytes_by_format[r.fmt] += (int64_t)r.rank * (r.PI + r.PJ) * (int64_t)fmt_size(r.fmt);
+            s.lowrank_entries += (int64_t)r.rank * (m + n);
+            s.total_columns += r.rank;
+            s.max_rank = std::max(s.max_rank, r.rank);
+            words += (double)r.rank * (m + n) * BITS[r.fmt] / 64.0;
+            words64 += (double)r.rank * (m + n);
+            bytes += (double)r.rank * (m + n) * fmt_size(r.fmt);
+        } else {
+            s.n_blocks_dense++;
+            s.dense_entries += m * n;
+            s.dense_bytes += r.PI * n * 8;
+            words += (double)(m * n);
+            words64 += (double)(m * n);
+            bytes += 8.0 * m * n;
+        }
+    }
+    const double io = h->opt.io_dtype == HH_IO_F32 ? 4.0 : 8.0;
+    s.storage_words = words;
+    s.storage_words_fp64 = words64;
+    s.matvec_bytes = bytes + 2.0 * io * h->plan.n;
+    double t2 = 0;
+    for (const auto& r : h->blocks)
+        t2 += (r.lowrank && r.b.kind != HH_BLK_DENSE_NEAR) ? r.nb2 : r.entry2;
+    s.norm2_total = t2;
+    s.build_seconds = seconds;
+}
+
+hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel* k, double tol,
+                        double eta, int switch_level, int leaf_size, const hh_options* opt) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!k) fail(HH_EINVAL, "kernel description is NULL");
+    if (k->type < HH_LOG || k->type > HH_DOUBLE_LAYER) fail(HH_EINVAL, "unknown kernel type");
+    if (!(tol > 0x1p-52 && tol < 1.0)) fail(HH_EINVAL, "tol must lie in (2^-52, 1)");
+    if (k->type == HH_DOUBLE_LAYER && !k->normals) fail(HH_EINVAL, "double-layer kernel needs normals");
+    if (!std::isfinite(k->scale) || !std::isfinite(k->h) || k->h < 0)
+        fail(HH_EINVAL, "kernel scale and h must be finite, h >= 0");
+    hh_options o{};
+    o.precision_mask = 0xF;
+    if (opt) o = *opt;
+    if (o.precision_mask == 0) o.precision_mask = 0xF;
+    if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
+    if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
+
+    std::unique_ptr<hh_handle> h(new hh_handle());
+    h->plan = make_plan(points, n, d, eta, switch_level, leaf_size);
+    HIPCHK(hipGetDevice(&h->device));
+    h->tol = tol;
+    h->opt = o;
+    h->kd = KernelDev{k->type, d, k->scale == 0.0 ? 1.0 : k->scale, k->h == 0.0 ? 1.0 : k->h};
+    const Plan& P = h->plan;
+    const bool uniform = o.uniform_fp64 != 0;
+
+    // tree-ordered points (and normals) on the device
+    std::vector<double> pt((size_t)n * d), nt;
+    for (int64_t t = 0; t < n; ++t)
+        for (int c = 0; c < d; ++c) pt[t * d + c] = points[P.perm[t] * d + c];
+    h->d_pts = upload(h->mem, pt);
+    if (k->type == HH_DOUBLE_LAYER) {
+        nt.resize((size_t)n * d);
+        for (int64_t t = 0; t < n; ++t)
+            for (int c = 0; c < d; ++c) {
+                double v = k->normals[P.perm[t] * d + c];
+                if (!std::isfinite(v)) fail(HH_EINVAL, "normals must be finite");
+                nt[t * d + c] = v;
+            }
+        h->d_nrm = upload(h->mem, nt);
+    }
+    layout(h.get());
+    h->d_tpad = upload(h->mem, h->tpad);
+    {
+        std::vector<int64_t> pmap(h->np, -1);
+        for (int64_t t = 0; t < n; ++t) pmap[h->tpad[t]] = P.perm[t];
+        h->d_pmap = upload(h->mem, pmap);
+    }
+
+    Builder B(h.get());
+    B.init();
+    std::vector<int64_t> cand, dense_list, near_adaptive;
+    for (size_t i = 0; i < h->blocks.size(); ++i) {
+        BlockRec& r = h->blocks[i];
+        const int kind = r.b.kind;
+        if (kind == HH_BLK_DIAG || (kind == HH_BLK_DENSE_NEAR && uniform)) {
+            dense_list.push_back((int64_t)i);
+        } else {
+            r.lowrank = true;
+            cand.push_back((int64_t)i);
+            if (kind == HH_BLK_DENSE_NEAR) near_adaptive.push_back((int64_t)i);
+        }
+    }
+    B.compress(cand);
+    B.dense(dense_list);
+
+    // Alg. 5: ||H~||^2; leaf neighbours of an H_s matrix enter with ||H_IJ||^2
+    double total2 = 0.0;
+    for (const auto& r : h->blocks) {
+        if (r.b.kind == HH_BLK_DENSE_NEAR || !r.lowrank) total2 += r.entry2;
+        else total2 += r.nb2;
+    }
+    // Alg. 3: storage precision per low-rank block
+    std::vector<int64_t> to_dense;
+    for (size_t i = 0; i < h->blocks.size(); ++i) {
+        BlockRec& r = h->blocks[i];
+        if (!r.lowrank) continue;
+        int fmt = HH_FMT_FP64;
+        if (!uniform) choose_lowrank_format(r, total2, d, tol, o.precision_mask, fmt);
+        r.fmt = fmt;
+        if (r.b.kind == HH_BLK_DENSE_NEAR) {
+            const int64_t m = r.b.ie - r.b.ib, nn = r.b.je - r.b.jb;
+            // keep the neighbour low-rank only when that saves storage
+            if (!((double)r.rank * (m + nn) * BITS[fmt] / 64.0 < (double)(m * nn)))
+                to_dense.push_back((int64_t)i);
+        }
+    }
+    for (int64_t i : to_dense) {
+        BlockRec& r = h->blocks[i];
+        double e2 = r.entry2;
+        r.u_ptr = r.v_ptr = nullptr;
+        B.dense({i});
+        r.entry2 = e2;
+        r.nb2 = e2;
+    }
+    B.pack();
+    build_tasks(h.get());
+    h->ws_R = 1;
+    h->xt = static_cast<double*>(h->mem.alloc((size_t)h->np * 8 + 256, true));
+    h->tb = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->ncols, 1) * 8 + 256, true));
+    if (h->all_fp64) {
+        // the fp64 store chunks are the arena: hand their ownership to the handle
+        for (void* p : B.store.ptrs) h->mem.ptrs.push_back(p);
+        B.store.ptrs.clear();
+    }
+    HIPCHK(hipDeviceSynchronize());
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(h.get(), secs);
+    return h.release();
+}
+
+}  // namespace hh
+
+namespace hh {
+hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
+    (void)src;
+    (void)opt;
+    fail(HH_ENOTSUP, "hh_derive is not available yet");
+}
+}  // namespace hh

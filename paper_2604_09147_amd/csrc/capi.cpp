@@ -1,0 +1,372 @@
+// C ABI of the H_h library: argument checks, error reporting, products,
+// inspection. Every entry point catches internal errors and returns a status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "handle.h"
+
+namespace hh {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+[[noreturn]] void fail(hh_status code, const std::string& msg) { throw Error{code, msg}; }
+
+hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel* k, double tol,
+                        double eta, int switch_level, int leaf_size, const hh_options* opt);
+hh_handle* derive_handle(const hh_handle* src, const hh_options* opt);
+
+static size_t fmt_size(int fmt) { return fmt == HH_FMT_FP64 ? 8 : fmt == HH_FMT_FP32 ? 4 : 2; }
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            fail(HH_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+static void ensure_workspace(hh_handle* h, int64_t R) {
+    if (R <= h->ws_R) return;
+    void* xt = h->mem.alloc((size_t)h->np * R * 8 + 256, true);
+    void* tb = h->mem.alloc((size_t)std::max<int64_t>(h->ncols, 1) * R * 8 + 256, true);
+    h->mem.release(h->xt);
+    h->mem.release(h->tb);
+    h->xt = static_cast<double*>(xt);
+    h->tb = static_cast<double*>(tb);
+    h->ws_R = R;
+}
+
+static void check_device(const hh_handle* h) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != h->device) fail(HH_EINVAL, "the current device is not the handle's device");
+}
+
+static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, void* stream,
+                    bool trans) {
+    if (!hc) fail(HH_EINVAL, "handle is NULL");
+    if (!x || !y) fail(HH_EINVAL, "x and y must be device pointers");
+    if (x == y) fail(HH_EINVAL, "x and y must not alias");
+    if (nrhs < 1 || nrhs > (1 << 16)) fail(HH_EINVAL, "nrhs must lie in [1, 65536]");
+    check_device(hc);
+    hh_handle* h = const_cast<hh_handle*>(hc);
+    ensure_workspace(h, nrhs);
+    Desc d{h->xt, h->tb, h->d_pmap, x, y, h->np, h->opt.io_dtype, 0};
+    const int R = (int)nrhs;
+    const TaskSet& S = trans ? h->bwd : h->fwd;
+    launch_gather(d, nullptr, 1, h->np, R, stream);
+    launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
+    launch_axpy(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), S.d_runs, S.d_druns, R, stream);
+    HIPCHK(hipGetLastError());
+}
+
+static void product_batch(const hh_handle* const* hs, int count, const void* const* x,
+                          void* const* y, int64_t nrhs, void* stream) {
+    if (!hs || !x || !y || count < 1) fail(HH_EINVAL, "batch needs count >= 1 handles, x and y");
+    if (nrhs < 1 || nrhs > (1 << 16)) fail(HH_EINVAL, "nrhs must lie in [1, 65536]");
+    const int io = hs[0] ? hs[0]->opt.io_dtype : 0;
+    std::vector<Desc> descs(count);
+    std::vector<DotTask> dot;
+    std::vector<LeafTask> leaf;
+    std::vector<Run> runs;
+    std::vector<DotRun> druns;
+    int64_t max_np = 0;
+    for (int t = 0; t < count; ++t) {
+        hh_handle* h = const_cast<hh_handle*>(hs[t]);
+        if (!h) fail(HH_EINVAL, "a handle in the batch is NULL");
+        if (!x[t] || !y[t] || x[t] == y[t]) fail(HH_EINVAL, "batch x / y pointers invalid");
+        if (h->opt.io_dtype != io) fail(HH_EINVAL, "handles of a batch must share io_dtype");
+        check_device(h);
+        for (int u = 0; u < t; ++u)
+            if (hs[u] == h) fail(HH_EINVAL, "a handle appears twice in the batch (shared workspace)");
+        ensure_workspace(h, nrhs);
+        descs[t] = Desc{h->xt, h->tb, h->d_pmap, x[t], y[t], h->np, io, 0};
+        max_np = std::max(max_np, h->np);
+        for (DotTask k : h->fwd.dot) {
+            k.hid = t;
+            dot.push_back(k);
+        }
+        const int32_t r0 = (int32_t)runs.size(), d0 = (int32_t)druns.size();
+        for (LeafTask k : h->fwd.leaf) {
+            k.hid = t;
+            k.run_begin += r0;
+            k.run_end += r0;
+            k.drun_begin += d0;
+            k.drun_end += d0;
+            leaf.push_back(k);
+        }
+        runs.insert(runs.end(), h->fwd.runs.begin(), h->fwd.runs.end());
+        druns.insert(druns.end(), h->fwd.druns.begin(), h->fwd.druns.end());
+    }
+    if (count > 65535) fail(HH_EINVAL, "at most 65535 handles per batch");
+    // staging buffers for this call (freed after the stream drains)
+    DevMem tmp;
+    auto up = [&](const void* src, size_t bytes) {
+        void* p = tmp.alloc(bytes + 16, false);
+        if (bytes) HIPCHK(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
+        return p;
+    };
+    Desc* dd = static_cast<Desc*>(up(descs.data(), descs.size() * sizeof(Desc)));
+    DotTask* dt = static_cast<DotTask*>(up(dot.data(), dot.size() * sizeof(DotTask)));
+    LeafTask* dl = static_cast<LeafTask*>(up(leaf.data(), leaf.size() * sizeof(LeafTask)));
+    Run* dr = static_cast<Run*>(up(runs.data(), runs.size() * sizeof(Run)));
+    DotRun* ddr = static_cast<DotRun*>(up(druns.data(), druns.size() * sizeof(DotRun)));
+    const int R = (int)nrhs;
+    launch_gather(descs[0], dd, count, max_np, R, stream);
+    launch_dot(descs[0], dd, dt, (int64_t)dot.size(), R, stream);
+    launch_axpy(descs[0], dd, dl, (int64_t)leaf.size(), dr, ddr, R, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+}
+
+static double decode(const void* base, int fmt, int64_t i) {
+    switch (fmt) {
+        case HH_FMT_FP64: return static_cast<const double*>(base)[i];
+        case HH_FMT_FP32: return static_cast<const float*>(base)[i];
+        case HH_FMT_FP16: return f16_to_f64(static_cast<const uint16_t*>(base)[i]);
+        default: return bf16_to_f64(static_cast<const uint16_t*>(base)[i]);
+    }
+}
+
+}  // namespace hh
+
+using namespace hh;
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                                          \
+    }                                                                                      \
+    catch (const hh::Error& e) {                                                           \
+        hh::set_error(e.msg);                                                              \
+        return e.code;                                                                     \
+    }                                                                                      \
+    catch (const std::bad_alloc&) {                                                        \
+        hh::set_error("host allocation failed");                                          \
+        return HH_ENOMEM;                                                                  \
+    }                                                                                      \
+    catch (const std::exception& e) {                                                      \
+        hh::set_error(e.what());                                                           \
+        return HH_EINTERNAL;                                                               \
+    }                                                                                      \
+    hh::set_error("");                                                                     \
+    return HH_OK;
+
+extern "C" {
+
+hh_status hh_build(const double* points, int64_t n, int d, const hh_kernel* k, double tol,
+                   double eta, int switch_level, int leaf_size, const hh_options* opt,
+                   hh_handle** out) {
+    if (out) *out = nullptr;
+    GUARD_BEGIN
+    if (!out) fail(HH_EINVAL, "out is NULL");
+    if (!points) fail(HH_EINVAL, "points is NULL");
+    *out = build_handle(points, n, d, k, tol, eta, switch_level, leaf_size, opt);
+    GUARD_END
+}
+
+hh_status hh_derive(const hh_handle* src, const hh_options* opt, hh_handle** out) {
+    if (out) *out = nullptr;
+    GUARD_BEGIN
+    if (!out || !src) fail(HH_EINVAL, "src and out must not be NULL");
+    check_device(src);
+    *out = derive_handle(src, opt);
+    GUARD_END
+}
+
+hh_status hh_matvec(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream) {
+    GUARD_BEGIN
+    product(h, x, y, nrhs, stream, false);
+    GUARD_END
+}
+
+hh_status hh_matvec_t(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream) {
+    GUARD_BEGIN
+    product(h, x, y, nrhs, stream, true);
+    GUARD_END
+}
+
+hh_status hh_matvec_batch(const hh_handle* const* hs, int count, const void* const* x,
+                          void* const* y, int64_t nrhs, void* stream) {
+    GUARD_BEGIN
+    product_batch(hs, count, x, y, nrhs, stream);
+    GUARD_END
+}
+
+hh_status hh_reserve(hh_handle* h, int64_t max_nrhs) {
+    GUARD_BEGIN
+    if (!h) fail(HH_EINVAL, "handle is NULL");
+    if (max_nrhs < 1 || max_nrhs > (1 << 16)) fail(HH_EINVAL, "max_nrhs must lie in [1, 65536]");
+    check_device(h);
+    ensure_workspace(h, max_nrhs);
+    GUARD_END
+}
+
+hh_status hh_get_stats(const hh_handle* h, hh_stats* out) {
+    GUARD_BEGIN
+    if (!h || !out) fail(HH_EINVAL, "NULL argument");
+    *out = h->stats;
+    GUARD_END
+}
+
+hh_status hh_block_count(const hh_handle* h, int64_t* count) {
+    GUARD_BEGIN
+    if (!h || !count) fail(HH_EINVAL, "NULL argument");
+    *count = (int64_t)h->blocks.size();
+    GUARD_END
+}
+
+hh_status hh_get_block(const hh_handle* h, int64_t index, hh_block_info* o) {
+    GUARD_BEGIN
+    if (!h || !o) fail(HH_EINVAL, "NULL argument");
+    if (index < 0 || index >= (int64_t)h->blocks.size()) fail(HH_EINVAL, "block index out of range");
+    const BlockRec& r = h->blocks[index];
+    *o = hh_block_info{};
+    o->level = r.b.level;
+    o->kind = r.lowrank ? r.b.kind : (r.b.kind == HH_BLK_DIAG ? HH_BLK_DIAG : HH_BLK_DENSE_NEAR);
+    o->rank = r.lowrank ? r.rank : 0;
+    o->format = r.fmt;
+    o->box_i = r.b.bi;
+    o->box_j = r.b.bj;
+    o->row_begin = r.b.ib;
+    o->row_end = r.b.ie;
+    o->col_begin = r.b.jb;
+    o->col_end = r.b.je;
+    o->exp_u = r.eU;
+    o->exp_v = r.eV;
+    o->lowrank = r.lowrank ? 1 : 0;
+    o->norm2 = r.nb2;
+    o->entry_norm2 = r.entry2;
+    o->tail_prev = r.tail_prev;
+    o->tail = r.tail;
+    GUARD_END
+}
+
+hh_status hh_get_block_factors(const hh_handle* h, int64_t index, double* U, double* V) {
+    GUARD_BEGIN
+    if (!h || !U) fail(HH_EINVAL, "NULL argument");
+    if (index < 0 || index >= (int64_t)h->blocks.size()) fail(HH_EINVAL, "block index out of range");
+    check_device(h);
+    HIPCHK(hipDeviceSynchronize());
+    const BlockRec& r = h->blocks[index];
+    const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
+    const int64_t rb = h->tpad[r.b.ib], cb = h->tpad[r.b.jb];
+    if (!r.lowrank) {
+        std::vector<double> D((size_t)r.PI * n);
+        HIPCHK(hipMemcpy(D.data(), r.d_ptr, D.size() * 8, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < m; ++i) U[i + j * m] = D[j * r.PI + h->tpad[r.b.ib + i] - rb];
+    } else if (r.rank > 0) {
+        if (!V) fail(HH_EINVAL, "V is NULL for a low-rank block");
+        const size_t es = fmt_size(r.fmt);
+        std::vector<char> bu((size_t)r.rank * r.PI * es), bv((size_t)r.rank * r.PJ * es);
+        HIPCHK(hipMemcpy(bu.data(), r.u_ptr, bu.size(), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(bv.data(), r.v_ptr, bv.size(), hipMemcpyDeviceToHost));
+        const double su = std::ldexp(1.0, r.eU), sv = std::ldexp(1.0, r.eV);
+        for (int64_t c = 0; c < r.rank; ++c) {
+            for (int64_t i = 0; i < m; ++i)
+                U[i + c * m] = su * decode(bu.data(), r.fmt, c * r.PI + h->tpad[r.b.ib + i] - rb);
+            for (int64_t j = 0; j < n; ++j)
+                V[j + c * n] = sv * decode(bv.data(), r.fmt, c * r.PJ + h->tpad[r.b.jb + j] - cb);
+        }
+    }
+    GUARD_END
+}
+
+hh_status hh_get_perm(const hh_handle* h, int64_t* perm) {
+    GUARD_BEGIN
+    if (!h || !perm) fail(HH_EINVAL, "NULL argument");
+    std::memcpy(perm, h->plan.perm.data(), h->plan.perm.size() * sizeof(int64_t));
+    GUARD_END
+}
+
+int hh_io_dtype(const hh_handle* h) { return h ? h->opt.io_dtype : -1; }
+int64_t hh_size(const hh_handle* h) { return h ? h->plan.n : -1; }
+
+void hh_free(hh_handle* h) {
+    if (!h) return;
+    int prev = -1;
+    const int dev = h->device;
+    (void)hipGetDevice(&prev);
+    if (prev != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    delete h;
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+}
+
+hh_status hh_plan_create(const double* points, int64_t n, int d, double eta, int switch_level,
+                         int leaf_size, hh_plan** out) {
+    if (out) *out = nullptr;
+    GUARD_BEGIN
+    if (!out || !points) fail(HH_EINVAL, "NULL argument");
+    hh_plan* p = new hh_plan();
+    try {
+        p->p = make_plan(points, n, d, eta, switch_level, leaf_size);
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    *out = p;
+    GUARD_END
+}
+
+hh_status hh_plan_info(const hh_plan* p, int32_t* L, int32_t* ell, int64_t* n_blocks) {
+    GUARD_BEGIN
+    if (!p) fail(HH_EINVAL, "plan is NULL");
+    if (L) *L = p->p.L;
+    if (ell) *ell = p->p.ell;
+    if (n_blocks) *n_blocks = (int64_t)p->p.blocks.size();
+    GUARD_END
+}
+
+hh_status hh_plan_blocks(const hh_plan* p, int32_t* level, int32_t* kind, int64_t* box_i,
+                         int64_t* box_j, int64_t* ib, int64_t* ie, int64_t* jb, int64_t* je) {
+    GUARD_BEGIN
+    if (!p) fail(HH_EINVAL, "plan is NULL");
+    const auto& B = p->p.blocks;
+    for (size_t i = 0; i < B.size(); ++i) {
+        if (level) level[i] = B[i].level;
+        if (kind) kind[i] = B[i].kind;
+        if (box_i) box_i[i] = B[i].bi;
+        if (box_j) box_j[i] = B[i].bj;
+        if (ib) ib[i] = B[i].ib;
+        if (ie) ie[i] = B[i].ie;
+        if (jb) jb[i] = B[i].jb;
+        if (je) je[i] = B[i].je;
+    }
+    GUARD_END
+}
+
+hh_status hh_plan_perm(const hh_plan* p, int64_t* perm) {
+    GUARD_BEGIN
+    if (!p || !perm) fail(HH_EINVAL, "NULL argument");
+    std::memcpy(perm, p->p.perm.data(), p->p.perm.size() * sizeof(int64_t));
+    GUARD_END
+}
+
+void hh_plan_free(hh_plan* p) { delete p; }
+
+hh_status hh_quantize(const double* in, int64_t n, int format, int e, double* out) {
+    GUARD_BEGIN
+    if (n < 0 || (n > 0 && (!in || !out))) fail(HH_EINVAL, "bad arrays");
+    if (format < HH_FMT_FP64 || format > HH_FMT_BF16) fail(HH_EINVAL, "unknown format");
+    const double s = std::ldexp(1.0, -e), b = std::ldexp(1.0, e);
+    for (int64_t i = 0; i < n; ++i) {
+        double v = in[i] * s, q;
+        switch (format) {
+            case HH_FMT_FP64: q = v; break;
+            case HH_FMT_FP32: q = (double)(float)v; break;
+            case HH_FMT_FP16: q = f16_to_f64(f64_to_f16_rne(v)); break;
+            default: q = bf16_to_f64(f64_to_bf16_rne(v)); break;
+        }
+        out[i] = q * b;
+    }
+    GUARD_END
+}
+
+const char* hh_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// The opaque handle behind hh_handle*.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "hh_build.h"
+#include "hh_internal.h"
+
+namespace hh {
+
+// Owned device allocation list; freed by the handle.
+struct DevMem {
+    std::vector<void*> ptrs;
+    void* alloc(size_t bytes, bool zero = true);
+    void release(void* p);
+    void free_all();
+    ~DevMem() { free_all(); }
+};
+
+struct TaskSet {                      // one direction of the product
+    std::vector<DotTask> dot;
+    std::vector<LeafTask> leaf;
+    std::vector<Run> runs;
+    std::vector<DotRun> druns;
+    DotTask* d_dot = nullptr;
+    LeafTask* d_leaf = nullptr;
+    Run* d_runs = nullptr;
+    DotRun* d_druns = nullptr;
+};
+
+}  // namespace hh
+
+struct hh_handle {
+    hh::Plan plan;
+    int device = 0;
+    hh::KernelDev kd{};
+    double tol = 0;
+    hh_options opt{};
+    std::vector<hh::BlockRec> blocks;
+    // padded layout
+    int64_t np = 0;
+    std::vector<int64_t> leaf_poff, leaf_psz, tpad;
+    // device data
+    hh::DevMem mem;
+    double* d_pts = nullptr;
+    double* d_nrm = nullptr;
+    int64_t* d_tpad = nullptr;
+    int64_t* d_pmap = nullptr;
+    hh::TaskSet fwd, bwd;
+    int64_t ncols = 0;
+    // product workspace
+    double* xt = nullptr;
+    double* tb = nullptr;
+    int64_t ws_R = 0;
+    // fp64 factors kept when every low-rank block is stored in fp64
+    bool all_fp64 = false;
+    hh_stats stats{};
+};

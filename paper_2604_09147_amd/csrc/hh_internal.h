@@ -1,0 +1,127 @@
+// Internal data structures of the H_h library (host and device).
+#pragma once
+
+#include <cstdint>
+#include <array>
+#include <string>
+#include <vector>
+
+#include "../../include/hh.h"
+
+namespace hh {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+struct Error {
+    hh_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(hh_status code, const std::string& msg);
+
+// ------------------------------------------------------------------- plan
+// Tree of Sec. 2.1 and the block partition of Alg. 1 (host only).
+struct Blk {
+    int32_t level, kind;
+    int64_t bi, bj;          // Morton box indices at `level`
+    int64_t ib, ie, jb, je;  // tree-order row / column ranges
+};
+
+struct Plan {
+    int64_t n = 0;
+    int d = 0, L = 0, ell = 0, leaf_size = 0;
+    double eta = 0;
+    std::vector<int64_t> perm;                 // tree position -> caller index
+    std::vector<std::vector<int64_t>> ranges;  // per level: 2 * 2^(d l) [beg, end)
+    std::vector<Blk> blocks;                   // canonical order (level, bi, bj)
+};
+
+Plan make_plan(const double* pts, int64_t n, int d, double eta, int switch_level,
+               int leaf_size);
+bool adm_s(const int64_t* ci, const int64_t* cj, int d, double eta);
+void box_coords(int64_t box, int level, int d, int64_t* c);
+
+// --------------------------------------------------------- device layouts
+// Padded tree coordinates: every leaf occupies round_up(n_leaf, 4) slots so
+// that a wave lane owning 4 consecutive rows always reads aligned vectors.
+constexpr int ROW_PAD = 4;
+
+// Per-handle device pointers the product kernels need (passed by value, or as
+// an array indexed by DotTask::hid / LeafTask::hid in a batched launch).
+struct Desc {
+    double* xt;              // gathered x, padded tree order, NP x R (row-major)
+    double* tb;              // column coefficients, C x R (row-major)
+    const int64_t* pmap;     // padded slot -> caller index (-1 = pad), NP entries
+    const void* x;           // caller x (N x R)
+    void* y;                 // caller y (N x R)
+    int64_t np;              // padded length
+    int32_t io;              // HH_IO_F64 / HH_IO_F32
+    int32_t pad_;
+};
+
+// Inner products of stored columns with a slice of the gathered vector:
+// tb[toff + c] = sum_j col_c[j] xt[xoff + j]  for c < ncols, j < P.
+struct DotTask {
+    const void* col0;        // first element of column 0; column c starts c * P later
+    int64_t xoff;            // padded row offset of the slice of xt
+    int64_t toff;            // coefficient index of column 0
+    int32_t P;               // column length (padded rows, multiple of 4)
+    int32_t ncols;
+    int32_t fmt;             // HH_FMT_*
+    int32_t hid;             // handle index in a batched launch
+};
+
+// A run of columns applied to one leaf: y_leaf += sum_c col_c coef_c scale,
+// coef_c = tb[toff + c] (low-rank block) or xt[toff + c] (dense block).
+struct Run {
+    const void* base;        // element (leaf row 0, column 0)
+    int64_t stride;          // elements between consecutive columns
+    int64_t toff;
+    double scale;            // 2^(eU + eV), exact
+    int32_t ncols;
+    int32_t fmt;             // HH_FMT_*; dense blocks are HH_FMT_FP64
+    int32_t from_x;
+    int32_t pad_;
+};
+
+// Transposed dense block applied to leaf mu: y_mu[j] += dot(D[:, j], xt_lambda).
+struct DotRun {
+    const double* base;      // column 0 of the block (column-major, padded rows)
+    int64_t xoff;            // padded offset of lambda in xt
+    int32_t P;               // padded rows of lambda
+    int32_t ncols;           // real points of mu
+};
+
+struct LeafTask {
+    int64_t poff;            // padded offset of the leaf
+    int32_t P;               // padded rows of the leaf
+    int32_t run_begin, run_end;
+    int32_t drun_begin, drun_end;
+    int32_t hid;
+};
+
+// Host record of one block after the build.
+struct BlockRec {
+    Blk b;
+    int32_t rank = 0, fmt = HH_FMT_FP64, eU = 0, eV = 0;
+    bool lowrank = false;
+    double nb2 = 0, entry2 = 0, tail_prev = 0, tail = 0;
+    const void* u_ptr = nullptr;      // stored factors (format fmt), padded-row layout
+    const void* v_ptr = nullptr;
+    const double* d_ptr = nullptr;    // dense block, PI x n column-major
+    int64_t col = -1;                 // coefficient index of column 0
+    int64_t PI = 0, PJ = 0;           // padded lengths of row / column clusters
+    int64_t pI = 0, pJ = 0;           // padded offsets of row / column clusters
+};
+
+// Kernel launch wrappers (defined in the .hip files).
+void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int R, void* stream);
+void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
+                int R, void* stream);
+void launch_axpy(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
+                 const Run* runs, const DotRun* druns, int R, void* stream);
+
+}  // namespace hh
+
+struct hh_plan {
+    hh::Plan p;
+};

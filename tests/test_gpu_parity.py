@@ -1,0 +1,152 @@
+"""GPU parity of the HIP library against the FP64 oracle (through the C ABI).
+
+Bars: structure (tree order, partition, ranks, formats) bit for bit, except
+decisions within 1e-6 of their threshold (ties); products within 1e-2 tol
+(relative 2-norm) of the oracle's H^ x, within 1e-12 of the fp64 product with
+the GPU's own exported factors, and within 10 tol of the dense product."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hh_oracle as O
+from parity_util import build_pair, compare_structure, exported_product, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _check_products(g, o, P, kern, tol, nrhs=1, trans=False, io="f64", dense=True, seed=1):
+    torch = _torch()
+    rng = np.random.default_rng(seed)
+    shape = (P.shape[0],) if nrhs == 1 else (P.shape[0], nrhs)
+    x = rng.standard_normal(shape)
+    dt = torch.float32 if io == "f32" else torch.float64
+    xd = torch.from_numpy(x).to(dt).cuda()
+    y = (g.matvec_t(xd) if trans else g.matvec(xd)).double().cpu().numpy()
+    xin = xd.double().cpu().numpy()          # the values the GPU actually saw
+    yo = (O.matvec_t(o, xin) if trans else O.matvec(o, xin))
+    ye = exported_product(g, xin, trans)
+    bar = max(1e-2 * tol, 2.0 ** -22) if io == "f32" else 1e-2 * tol
+    assert rel(y, yo) <= bar, (rel(y, yo), bar)
+    if io == "f64":
+        assert rel(y, ye) <= 1e-12, rel(y, ye)
+    if dense:
+        k = O.Kernel(kern.kind, kern.scale, kern.h, kern.normals)
+        yd = O.dense_matvec_t(P, k, xin) if trans else O.dense_matvec(P, k, xin)
+        assert rel(y, yd) <= 10 * tol, rel(y, yd)
+    return y
+
+
+def test_plain_2d_log_small_config():
+    # N = 4096 uniform in [0,1]^2, log r, leaf 64, eta 1, switch 2, tol 1e-8, {fp64, fp32, fp16}
+    p = W.cfg_plain_small()
+    g, o = build_pair(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, mask=p.mask)
+    ties = compare_structure(g, o)
+    assert not ties
+    s = g.stats()
+    assert s["L"] == 3 and s["ell"] == 2
+    _check_products(g, o, p.points, O.Kernel(p.kernel), p.tol)
+    _check_products(g, o, p.points, O.Kernel(p.kernel), p.tol, trans=True)
+
+
+@pytest.mark.parametrize("nrhs", [2, 5, 9])
+def test_multiple_rhs(nrhs):
+    p = W.cfg_plain_small(seed=5, n=3000)
+    g, o = build_pair(p.points, p.kernel, 1e-6, p.eta, -1, 48)
+    compare_structure(g, o)
+    _check_products(g, o, p.points, O.Kernel(p.kernel), 1e-6, nrhs=nrhs, dense=False)
+    _check_products(g, o, p.points, O.Kernel(p.kernel), 1e-6, nrhs=nrhs, trans=True, dense=False)
+
+
+@pytest.mark.parametrize("kind,d,tol,eta,ell,mask", [
+    (W.INV_R, 3, 1e-4, 1.5, -1, 0xF), (W.INV_R2, 3, 1e-3, math.sqrt(3), 2, 0xF),
+    (W.GAUSS, 3, 1e-6, math.sqrt(3), -1, 0xF), (W.MATERN, 2, 1e-3, 1.0, 0, 0xF),
+    (W.LOG, 2, 1e-3, math.sqrt(2), 4, 0xF), (W.LOG, 1, 1e-8, 1.0, 3, 0x7),
+    (W.INV_R, 2, 1e-2, 1.0, -1, 0x9)])
+def test_kernels_levels_and_formats(kind, d, tol, eta, ell, mask):
+    rng = np.random.default_rng(kind * 10 + d)
+    n = 2311
+    P = rng.random((n, d)) * (2.0 if kind == W.GAUSS else 1.0)
+    leaf = 16 if d == 1 else 24
+    g, o = build_pair(P, kind, tol, eta, ell, leaf, mask=mask)
+    compare_structure(g, o)
+    _check_products(g, o, P, O.Kernel(kind), tol)
+    _check_products(g, o, P, O.Kernel(kind), tol, trans=True)
+
+
+def test_double_layer_nonsymmetric_and_f32_io():
+    rng = np.random.default_rng(55)
+    n = 2000
+    P = np.concatenate([W.sphere_surface(n // 2, 3, rng), W.ball_interior(n - n // 2, 3, rng)])
+    nrm = W.unit_normals(n, 3, rng)
+    tol = 1e-6
+    g, o = build_pair(P, W.DOUBLE_LAYER, tol, 1.5, -1, 32, normals=nrm, io="f32")
+    compare_structure(g, o)
+    k = O.Kernel(W.DOUBLE_LAYER, normals=nrm)
+    _check_products(g, o, P, k, tol, io="f32")
+    _check_products(g, o, P, k, tol, io="f32", trans=True)
+    _check_products(g, o, P, k, tol, io="f32", nrhs=4, dense=False)
+
+
+def test_randomized_compression_path():
+    # leaf 256 at N = 4096 in 2D gives L = 2; the level-1 neighbours are 1024 x 1024
+    # blocks, compressed by the randomized range finder on both sides
+    rng = np.random.default_rng(77)
+    P = rng.random((4096, 2))
+    tol = 1e-6
+    g, o = build_pair(P, W.INV_R, tol, 1.0, 1, 256, seed=123)
+    assert any(sb.comp is not None and sb.comp.sketch > 0 for sb in o.blocks)
+    compare_structure(g, o)
+    _check_products(g, o, P, O.Kernel(W.INV_R), tol)
+
+
+def test_uniform_fp64_and_hs_special_case():
+    rng = np.random.default_rng(8)
+    P = rng.random((1800, 2))
+    tol = 1e-4
+    for uniform in (True, False):
+        g, o = build_pair(P, W.INV_R, tol, math.sqrt(2), 4, 8, uniform=uniform)   # ell = L
+        assert g.stats()["L"] == 4
+        compare_structure(g, o)
+        _check_products(g, o, P, O.Kernel(W.INV_R), tol)
+        _check_products(g, o, P, O.Kernel(W.INV_R), tol, trans=True)
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 1000])
+def test_tiny_and_ragged_sizes(n):
+    rng = np.random.default_rng(n)
+    P = rng.random((n, 2))
+    g, o = build_pair(P, W.INV_R, 1e-6, 1.0, -1, 64)
+    compare_structure(g, o)
+    _check_products(g, o, P, O.Kernel(W.INV_R), 1e-6)
+    _check_products(g, o, P, O.Kernel(W.INV_R), 1e-6, trans=True)
+
+
+def test_clustered_points_with_empty_boxes():
+    rng = np.random.default_rng(4)
+    P = np.concatenate([rng.random((1500, 3)) * 0.05, rng.random((700, 3)),
+                        np.repeat(rng.random((10, 3)), 3, axis=0)])
+    g, o = build_pair(P, W.INV_R, 1e-5, 1.5, -1, 16)
+    compare_structure(g, o)
+    _check_products(g, o, P, O.Kernel(W.INV_R), 1e-5)
+    _check_products(g, o, P, O.Kernel(W.INV_R), 1e-5, trans=True)
+
+
+def test_products_are_bitwise_reproducible():
+    torch = _torch()
+    p = W.cfg_plain_small(seed=9, n=2500)
+    g, _ = build_pair(p.points, p.kernel, 1e-6, 1.0, -1, 32)
+    x = torch.randn(2500, dtype=torch.float64, device="cuda")
+    y1 = g.matvec(x).cpu().numpy()
+    y2 = g.matvec(x).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    X = torch.randn(2500, 3, dtype=torch.float64, device="cuda")
+    assert np.array_equal(g.matvec_t(X).cpu().numpy(), g.matvec_t(X).cpu().numpy())
