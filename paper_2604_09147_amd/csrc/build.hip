@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -206,11 +208,17 @@ struct Builder {
                                                M * N, S, p, U, (rocblas_int)M, M * p, Vt,
                                                (rocblas_int)p, p * N, E, p, rocblas_outofplace,
                                                info, B));
+        std::vector<rocblas_int> hinfo(B);
+        HIPCHK(hipMemcpy(hinfo.data(), info, B * sizeof(rocblas_int), hipMemcpyDeviceToHost));
+        // SVDs that did not converge in the padded batch are recomputed alone at
+        // their exact size (U, Vt and S of that item are overwritten in place)
+        for (int b = 0; b < B; ++b)
+            if (hinfo[b] != 0) retry_exact(idx[b], U + (int64_t)b * M * p, M, Vt + (int64_t)b * p * N,
+                                           p, S + (int64_t)b * p, p, hinfo[b], M, N);
         RankItem* dri = meta(ri, cv);
         launch_rank(dri, B, eps2, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpy(ri.data(), dri, B * sizeof(RankItem), hipMemcpyDeviceToHost));
-        check_info(info, B);
         std::vector<int> ranks(B);
         for (int b = 0; b < B; ++b) {
             record_rank(idx[b], ri[b]);
@@ -241,6 +249,51 @@ struct Builder {
         if (!fi.empty()) launch_finalize(meta(fi, cv), (int)fi.size(), h->d_tpad, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipDeviceSynchronize());
+    }
+
+    // One block through the non-batched SVD at its exact size, results written
+    // into the batch's output slots (column-major U with ldu, Vt with ldv, S).
+    void retry_exact(int64_t bi, double* Uo, int64_t ldu, double* Vto, int64_t ldv, double* So,
+                     int64_t ps, int first_info, int64_t M, int64_t N) {
+        const Blk& k = h->blocks[bi].b;
+        const int64_t m = k.ie - k.ib, n = k.je - k.jb, p = std::min(m, n);
+        DevMem tmp;
+        double* A = static_cast<double*>(tmp.alloc((size_t)m * n * 8, false));
+        double* U1 = static_cast<double*>(tmp.alloc((size_t)m * p * 8, false));
+        double* V1 = static_cast<double*>(tmp.alloc((size_t)p * n * 8, false));
+        double* S1 = static_cast<double*>(tmp.alloc((size_t)p * 8, false));
+        double* E1 = static_cast<double*>(tmp.alloc((size_t)p * 8 + 8, false));
+        rocblas_int* inf = static_cast<rocblas_int*>(tmp.alloc(64, false));
+        GenItem g{k.ib, k.jb, m, n, A, m, 0, 0};
+        GenItem* dg = static_cast<GenItem*>(tmp.alloc(sizeof(GenItem), false));
+        HIPCHK(hipMemcpy(dg, &g, sizeof(GenItem), hipMemcpyHostToDevice));
+        rocblas_int hi = 1;
+        const rocblas_workmode modes[2] = {rocblas_outofplace, rocblas_inplace};
+        for (int t = 0; t < 2 && hi != 0; ++t) {
+            launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, dg, 1, m, n, m * n, st);
+            RBCHK(rocsolver_dgesvd(rb, rocblas_svect_singular, rocblas_svect_singular,
+                                   (rocblas_int)m, (rocblas_int)n, A, (rocblas_int)m, S1, U1,
+                                   (rocblas_int)m, V1, (rocblas_int)p, E1, modes[t], inf));
+            HIPCHK(hipMemcpy(&hi, inf, sizeof(hi), hipMemcpyDeviceToHost));
+            if (verbose())
+                fprintf(stderr, "hh: block %lld (%lld x %lld, padded %lld x %lld) batched SVD info %d; "
+                        "alone (mode %d): info %d\n", (long long)bi, (long long)m, (long long)n,
+                        (long long)M, (long long)N, first_info, t, hi);
+        }
+        if (hi != 0)
+            fail(HH_EINTERNAL, "SVD of block " + std::to_string(bi) + " did not converge");
+        HIPCHK(hipMemset(So, 0, ps * 8));
+        HIPCHK(hipMemcpy(So, S1, p * 8, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemset2D(Uo, ldu * 8, 0, ldu * 8, p));
+        HIPCHK(hipMemcpy2D(Uo, ldu * 8, U1, m * 8, m * 8, p, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemset2D(Vto, ldv * 8, 0, ldv * 8, N));
+        HIPCHK(hipMemcpy2D(Vto, ldv * 8, V1, p * 8, p * 8, n, hipMemcpyDeviceToDevice));
+        HIPCHK(hipDeviceSynchronize());
+    }
+
+    static bool verbose() {
+        const char* v = getenv("HH_VERBOSE");
+        return v && v[0] && v[0] != '0';
     }
 
     void check_info(const rocblas_int* dinfo, int B) {
@@ -287,7 +340,7 @@ struct Builder {
         double* e2 = cv.take<double>(B);
         double* part = cv.take<double>((size_t)B * nch);
         double* dummy = cv.take<double>(16);
-        rocblas_int* info = cv.take<rocblas_int>(B);
+        rocblas_int* info = cv.take<rocblas_int>(4 * B);   // one slot per SVD call
         std::vector<GenItem> gi(B);
         std::vector<SumItem> si(B);
         std::vector<SketchItem> ski(B);
@@ -307,13 +360,13 @@ struct Builder {
         // range finder with one power iteration
         RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, iN, &one, H, iM, M * N, Om, iN,
                                             N * s, &zero, Y, iM, M * s, B));
-        orth(Y, M, s, Q, S2, E2, dummy, info, B);
+        orth(Y, M, s, Q, S2, E2, dummy, info + B, B);
         RBCHK(rocblas_dgemm_strided_batched(rb, TR, NT, iN, is, iM, &one, H, iM, M * N, Q, iM,
                                             M * s, &zero, Z, iN, N * s, B));
-        orth(Z, N, s, Q2, S2, E2, dummy, info, B);
+        orth(Z, N, s, Q2, S2, E2, dummy, info + 2 * B, B);
         RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, iN, &one, H, iM, M * N, Q2, iN,
                                             N * s, &zero, Y, iM, M * s, B));
-        orth(Y, M, s, Q, S2, E2, dummy, info, B);
+        orth(Y, M, s, Q, S2, E2, dummy, info + 3 * B, B);
         // B = Q^T H, then H <- H - Q B and its Frobenius norm (the discarded part)
         RBCHK(rocblas_dgemm_strided_batched(rb, TR, NT, is, iN, iM, &one, Q, iM, M * s, H, iM,
                                             M * N, &zero, Bm, is, s * N, B));
@@ -343,7 +396,7 @@ struct Builder {
                                             s * s, &zero, Y, iM, M * s, B));
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpy(ri.data(), dri, B * sizeof(RankItem), hipMemcpyDeviceToHost));
-        check_info(info, B);
+        check_info(info, 4 * B);
         std::vector<int64_t> acc_idx, retry;
         std::vector<int> acc_rank, acc_pos;
         for (int b = 0; b < B; ++b) {
@@ -396,14 +449,20 @@ struct Builder {
                             4 * s + 3 + (M * N) / SUM_CHUNK + 1) + 2048;
     }
 
-    // Greedy batches of blocks sorted by size, bounded by the scratch budget.
+    // Size bucket: dimensions within a factor 2^(1/4) share a bucket, so zero
+    // padding to the batch maximum wastes at most ~19% per dimension.
+    static int bucket(int64_t v) { return (int)std::ceil(4.0 * std::log2((double)std::max<int64_t>(v, 1))); }
+
+    // Greedy batches of same-bucket blocks, bounded by the scratch budget.
     template <class F, class G>
     void batched(std::vector<int64_t> list, F item_bytes, G run) {
+        auto key = [&](int64_t a) {
+            const Blk& x = h->blocks[a].b;
+            return std::make_pair(bucket(x.ie - x.ib), bucket(x.je - x.jb));
+        };
         std::sort(list.begin(), list.end(), [&](int64_t a, int64_t b) {
-            const Blk &x = h->blocks[a].b, &y = h->blocks[b].b;
-            int64_t xm = x.ie - x.ib, ym = y.ie - y.ib, xn = x.je - x.jb, yn = y.je - y.jb;
-            if (xm != ym) return xm > ym;
-            if (xn != yn) return xn > yn;
+            auto ka = key(a), kb = key(b);
+            if (ka != kb) return ka > kb;
             return a < b;
         });
         size_t i = 0;
@@ -411,7 +470,8 @@ struct Builder {
         while (i < list.size()) {
             std::vector<int64_t> batch;
             int64_t M = 0, N = 0;
-            while (i < list.size() && batch.size() < 4096) {
+            const auto k0 = key(list[i]);
+            while (i < list.size() && batch.size() < 4096 && key(list[i]) == k0) {
                 const Blk& k = h->blocks[list[i]].b;
                 int64_t M2 = std::max<int64_t>(M, k.ie - k.ib), N2 = std::max<int64_t>(N, k.je - k.jb);
                 if (!batch.empty() && item_bytes(M2, N2) * (batch.size() + 1) > budget) break;

@@ -173,6 +173,16 @@ def quantize(values, fmt: int, e: int = 0) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ handles
+def _torch_context() -> None:
+    """Let torch create its device context before the library's first HIP call
+    (both then share the one initialised runtime)."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
 def _stream_ptr(stream=None):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -199,6 +209,7 @@ class HMatrix:
                 k.normals = _dptr(self._normals)
             o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io_dtype == "f32" else IO_F64,
                         int(seed))
+            _torch_context()
             hp = _P()
             _check(lib().hh_build(_dptr(pts), n, d, C.byref(k), float(tol), float(eta),
                                   int(switch_level), int(leaf_size), C.byref(o), C.byref(hp)))

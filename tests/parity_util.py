@@ -68,12 +68,17 @@ def compare_structure(g, o) -> list:
 
 
 def exported_product(g, x, trans=False):
-    """fp64 product with the GPU's own stored factors (exported and decoded)."""
+    """fp64 product with the GPU's own stored factors (exported and decoded),
+    plus an elementwise bound on the kernel's deviation from it: fp16 / bf16
+    blocks form their inner products in fp32 (x rounded to fp32, products and
+    lane sums of about P/64 terms in fp32), so per such block
+    |err| <= gamma_P |A| (|B|^T |x|) with gamma_P = (P/64 + 4) 2^-24."""
     perm = g.perm()
     n = g.n
     x2 = np.asarray(x, dtype=np.float64).reshape(n, -1)
     xt = x2[perm]
     yt = np.zeros_like(xt)
+    bt = np.zeros_like(xt)
     bl = g.blocks()
     for q in range(bl["level"].size):
         ib, ie, jb, je = (int(bl[k][q]) for k in ("row_begin", "row_end", "col_begin", "col_end"))
@@ -82,9 +87,12 @@ def exported_product(g, x, trans=False):
             if bl["rank"][q] == 0:
                 continue
             if trans:
-                yt[jb:je] += B @ (A.T @ xt[ib:ie])
-            else:
-                yt[ib:ie] += A @ (B.T @ xt[jb:je])
+                A, B, ib, ie, jb, je = B, A, jb, je, ib, ie
+            yt[ib:ie] += A @ (B.T @ xt[jb:je])
+            if bl["format"][q] in (W.FMT_FP16, W.FMT_BF16):
+                P = 4 * (-(-(je - jb) // 4)) + 64          # padded length, generous
+                gam = (P / 64.0 + 4.0) * 2.0 ** -24
+                bt[ib:ie] += gam * (np.abs(A) @ (np.abs(B).T @ np.abs(xt[jb:je])))
         else:
             if trans:
                 yt[jb:je] += A.T @ xt[ib:ie]
@@ -92,7 +100,13 @@ def exported_product(g, x, trans=False):
                 yt[ib:ie] += A @ xt[jb:je]
     y = np.empty_like(yt)
     y[perm] = yt
-    return y.reshape(np.shape(x))
+    b = np.empty_like(bt)
+    b[perm] = bt
+    return y.reshape(np.shape(x)), b.reshape(np.shape(x))
+
+
+def within_kernel_bound(y, ye, bound, slack=1e-12) -> bool:
+    return bool(np.all(np.abs(y - ye) <= bound + slack * np.max(np.abs(ye))))
 
 
 def rel(a, b) -> float:

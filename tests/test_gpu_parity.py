@@ -2,8 +2,9 @@
 
 Bars: structure (tree order, partition, ranks, formats) bit for bit, except
 decisions within 1e-6 of their threshold (ties); products within 1e-2 tol
-(relative 2-norm) of the oracle's H^ x, within 1e-12 of the fp64 product with
-the GPU's own exported factors, and within 10 tol of the dense product."""
+(relative 2-norm) of the oracle's H^ x, within 10 tol of the dense product, and
+elementwise within the fp32-arithmetic error bound of fp16 / bf16 blocks (plus
+1e-12 max|y|) of the fp64 product with the GPU's own exported factors."""
 import math
 
 import numpy as np
@@ -11,7 +12,8 @@ import pytest
 
 import workloads as W
 from oracle import hh_oracle as O
-from parity_util import build_pair, compare_structure, exported_product, rel
+from parity_util import (build_pair, compare_structure, exported_product, rel,
+                         within_kernel_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -33,11 +35,12 @@ def _check_products(g, o, P, kern, tol, nrhs=1, trans=False, io="f64", dense=Tru
     y = (g.matvec_t(xd) if trans else g.matvec(xd)).double().cpu().numpy()
     xin = xd.double().cpu().numpy()          # the values the GPU actually saw
     yo = (O.matvec_t(o, xin) if trans else O.matvec(o, xin))
-    ye = exported_product(g, xin, trans)
+    ye, bound = exported_product(g, xin, trans)
     bar = max(1e-2 * tol, 2.0 ** -22) if io == "f32" else 1e-2 * tol
     assert rel(y, yo) <= bar, (rel(y, yo), bar)
     if io == "f64":
-        assert rel(y, ye) <= 1e-12, rel(y, ye)
+        # the kernel against the fp64 product of its own stored factors
+        assert within_kernel_bound(y, ye, bound), rel(y, ye)
     if dense:
         k = O.Kernel(kern.kind, kern.scale, kern.h, kern.normals)
         yd = O.dense_matvec_t(P, k, xin) if trans else O.dense_matvec(P, k, xin)
