@@ -108,6 +108,11 @@ typedef struct {
                                              product: factors + dense + x + y          */
     double norm2_total;                   /* ||H~||_F^2 from Alg. 5                    */
     double build_seconds;                 /* wall time of hh_build / hh_derive         */
+    double phase_bytes[3];                /* algorithmic HBM bytes of the three kernels
+                                             of one nrhs = 1 product: [0] gather (x in,
+                                             gathered x out), [1] inner products (V
+                                             factors), [2] leaf accumulation (U factors,
+                                             dense blocks, y out)                      */
 } hh_stats;
 
 typedef struct {                          /* one block, canonical order (level, i, j)  */
@@ -166,6 +171,13 @@ hh_status hh_matvec(const hh_handle* h, const void* x, void* y, int64_t nrhs, vo
 /* hh_matvec_t: y = H^^T x: y_J += V_b (U_b^T x_I), y_J += H_IJ^T x_I (dense
  * blocks transposed inside the kernel). Same conventions as hh_matvec. */
 hh_status hh_matvec_t(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream);
+
+/* hh_matvec_timed: one product (trans = 0: H^ x, 1: H^^T x) exactly as
+ * hh_matvec / hh_matvec_t, with HIP events recorded on `stream` around each of
+ * its three kernels; waits for the stream and returns the elapsed milliseconds
+ * of [gather, inner products, leaf accumulation] in phase_ms (HOST, 3). */
+hh_status hh_matvec_timed(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream,
+                          int trans, double* phase_ms);
 
 /* hh_matvec_batch: y_t = H_t^ x_t for `count` independent handles in one pass
  * of the kernels (one launch per phase). Every handle must share io_dtype and

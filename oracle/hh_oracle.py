@@ -36,8 +36,8 @@ R4 admissibility on tree boxes: diam = sqrt(d) h, dist = h sqrt(S) with
    as admissible through a relative slack of 2^-40 (this is what reproduces the
    FMM list sizes 27/8 and 189/26 the paper states for eta = sqrt(d)).
 R5 weak interaction list = the 2^d - 1 siblings (|IL_w| = 2^d - 1).
-R6 compression: exact SVD when min(m, n) <= 512; otherwise a randomized range
-   finder (Rademacher sketch from SplitMix64, one power iteration, width 32
+R6 compression: exact SVD when min(m, n) <= 64; otherwise a randomized range
+   finder (Rademacher sketch from SplitMix64, one power iteration, width 64
    doubling, oversampling 16) whose truncation error ||H - QB||_F^2 is summed
    directly, so the per-block bound ||H_b - H~_b|| <= eps ||H_b|| stays
    certified. Rank k = smallest k whose discarded tail <= eps^2 ||H_b||_F^2.
@@ -69,8 +69,8 @@ T_FAR, T_NEAR, T_WEAK, T_DIAG, T_DENSE_NEAR = 0, 1, 2, 3, 4
 TYPE_NAMES = {T_FAR: "IL_s", T_NEAR: "N_s", T_WEAK: "IL_w", T_DIAG: "diag",
               T_DENSE_NEAR: "N_s dense"}
 
-EXACT_SVD_MAX = 512      # R6
-SKETCH_START = 32
+EXACT_SVD_MAX = 64       # R6
+SKETCH_START = 64
 OVERSAMPLE = 16
 TIE_SLACK = 2.0 ** -40   # R4
 

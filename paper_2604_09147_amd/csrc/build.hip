@@ -23,6 +23,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <string>
 
 #include "handle.h"
 
@@ -42,8 +43,8 @@ namespace hh {
                  std::string(#x) + ": rocblas status " + std::to_string((int)s_));         \
     } while (0)
 
-constexpr int EXACT_SVD_MAX = 512;
-constexpr int SKETCH_START = 32;
+constexpr int EXACT_SVD_MAX = 64;
+constexpr int SKETCH_START = 64;
 constexpr int OVERSAMPLE = 16;
 constexpr int64_t SUM_CHUNK = 65536;
 constexpr int64_t DOT_TASK_ELEMS = 65536;
@@ -114,6 +115,43 @@ struct Builder {
     std::vector<double*> store_chunks;   // fp64 factors (freed after packing unless kept)
     DevMem store;
 
+    // per-step wall time (synchronised) when HH_VERBOSE is set
+    std::map<std::string, double> tsum;
+    std::chrono::steady_clock::time_point tmark;
+    void tick() {
+        if (!verbose()) return;
+        (void)hipDeviceSynchronize();
+        tmark = std::chrono::steady_clock::now();
+    }
+    void tock(const char* what) {
+        if (!verbose()) return;
+        (void)hipDeviceSynchronize();
+        auto now = std::chrono::steady_clock::now();
+        tsum[what] += std::chrono::duration<double>(now - tmark).count();
+        tmark = now;
+    }
+    void report_times() {
+        if (!verbose()) return;
+        for (auto& kv : tsum) fprintf(stderr, "hh:   %-14s %8.2f s\n", kv.first.c_str(), kv.second);
+        fflush(stderr);
+    }
+
+    // progress of the compression, printed from the batch loop when HH_VERBOSE is set
+    int64_t done = 0, total_cand = 0;
+    std::chrono::steady_clock::time_point t_start = std::chrono::steady_clock::now(),
+                                          t_last = t_start;
+    void progress(int64_t finished, const char* what, bool force = false) {
+        done += finished;
+        if (!verbose()) return;
+        auto now = std::chrono::steady_clock::now();
+        if (!force && std::chrono::duration<double>(now - t_last).count() < 10.0) return;
+        t_last = now;
+        fprintf(stderr, "hh: %s: %lld / %lld admissible blocks compressed, %.1f s\n", what,
+                (long long)done, (long long)total_cand,
+                std::chrono::duration<double>(now - t_start).count());
+        fflush(stderr);
+    }
+
     explicit Builder(hh_handle* hh) : h(hh), eps2(hh->tol * hh->tol) {}
     ~Builder() {
         if (rb) rocblas_destroy_handle(rb);
@@ -126,13 +164,13 @@ struct Builder {
         return d;
     }
 
-    void init() {
+    void init(size_t cap = (size_t)16 << 30) {
         RBCHK(rocblas_create_handle(&rb));
         RBCHK(rocblas_set_stream(rb, st));
         size_t freeb = 0, totalb = 0;
         HIPCHK(hipMemGetInfo(&freeb, &totalb));
         size_t want = freeb / 5;
-        if (want > ((size_t)16 << 30)) want = (size_t)16 << 30;
+        if (want > cap) want = cap;
         if (want < ((size_t)64 << 20)) want = (size_t)64 << 20;
         scratch_bytes = want;
         scratch = static_cast<char*>(scratch_mem.alloc(scratch_bytes, false));
@@ -201,13 +239,16 @@ struct Builder {
             r.pmin = (int)std::min(k.ie - k.ib, k.je - k.jb);
             ri[b] = r;
         }
+        tick();
         launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, meta(gi, cv), B, M, N, M * N, st);
         launch_sumsq(meta(si, cv), B, M * N, part, SUM_CHUNK, nrm, st);
+        tock("x.gen");
         RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_singular,
                                                (rocblas_int)M, (rocblas_int)N, A, (rocblas_int)M,
                                                M * N, S, p, U, (rocblas_int)M, M * p, Vt,
                                                (rocblas_int)p, p * N, E, p, rocblas_outofplace,
                                                info, B));
+        tock("x.gesvd");
         std::vector<rocblas_int> hinfo(B);
         HIPCHK(hipMemcpy(hinfo.data(), info, B * sizeof(rocblas_int), hipMemcpyDeviceToHost));
         // SVDs that did not converge in the padded batch are recomputed alone at
@@ -231,7 +272,8 @@ struct Builder {
             if (!ranks[b]) continue;
             FinItem f{};
             f.U = U + (int64_t)b * M * p;
-            f.Vt = Vt + (int64_t)b * p * N;
+            f.V = Vt + (int64_t)b * p * N;
+            f.v_rows = 1;
             f.sigma = S + (int64_t)b * p;
             f.Uout = (double*)r.u_ptr;
             f.Vout = (double*)r.v_ptr;
@@ -249,6 +291,7 @@ struct Builder {
         if (!fi.empty()) launch_finalize(meta(fi, cv), (int)fi.size(), h->d_tpad, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipDeviceSynchronize());
+        tock("x.rank+fin");
     }
 
     // One block through the non-batched SVD at its exact size, results written
@@ -303,25 +346,159 @@ struct Builder {
             if (hi[b] != 0) fail(HH_EINTERNAL, "SVD did not converge (info " + std::to_string(hi[b]) + ")");
     }
 
-    void orth(double* Y, int64_t rows, int64_t s, double* Q, double* S2, double* E2, double* dummy,
-              rocblas_int* info, int B) {
-        RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_none,
-                                               (rocblas_int)rows, (rocblas_int)s, Y,
-                                               (rocblas_int)rows, rows * s, S2, s, Q,
-                                               (rocblas_int)rows, rows * s, dummy, 1, 1, E2, s,
-                                               rocblas_outofplace, info, B));
+    // Orthonormal basis of each rows x s item of Y (column-major, stride rows s):
+    // Householder QR (geqrf) and the explicit Q = [I; 0] - V T V1^T with
+    // T = (diag(1/tau) + striu(V^T V))^-1. Y is overwritten; R (s x s) optional.
+    struct QrWork {
+        double *tau, *Vm, *G, *Tinv, *T, *W, *W2, *W3;
+    };
+    QrWork qr_work(Carver& cv, int B, int64_t rows_max, int s) {
+        QrWork w;
+        w.W2 = cv.take<double>((size_t)B * 32 * s);
+        w.W3 = cv.take<double>((size_t)B * 32 * s);
+        w.tau = cv.take<double>((size_t)B * s);
+        w.Vm = cv.take<double>((size_t)B * rows_max * s);
+        w.G = cv.take<double>((size_t)B * s * s);
+        w.Tinv = cv.take<double>((size_t)B * s * s);
+        w.T = cv.take<double>((size_t)B * s * s);
+        w.W = cv.take<double>((size_t)B * s * s);
+        return w;
+    }
+    // Householder QR in place (geqrf layout). Up to 64 columns one kernel per
+    // item; wider matrices in 32-column panels whose trailing columns are
+    // updated with the compact-WY form (I - V T V^T)^T through batched GEMMs.
+    void house_qr(double* Y, int64_t rows, int s, const QrWork& w, int B) {
+        const int64_t strideA = rows * s;
+        if (s <= 64) {
+            launch_house_qr(Y, rows, strideA, w.tau, s, rows, s, B, st);
+            return;
+        }
+        const int nb = 32;
+        const double one = 1.0, zero = 0.0, mone = -1.0;
+        const int64_t nn = (int64_t)nb * nb;
+        for (int p0 = 0; p0 < s; p0 += nb) {
+            const int pw = std::min(nb, s - p0);
+            const int64_t mp = rows - p0;
+            double* panel = Y + (int64_t)p0 * rows + p0;
+            launch_house_qr(panel, rows, strideA, w.tau + p0, s, mp, pw, B, st);
+            const int rest = s - p0 - pw;
+            if (rest <= 0) break;
+            // V (mp x pw, in w.Vm), T (pw x pw, in w.T): T = (diag(1/tau) + striu(V^T V))^-1
+            launch_panel_v(panel, rows, strideA, w.tau + p0, s, w.Vm, w.T, mp, pw, B, st);
+            RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_transpose,
+                                                rocblas_operation_none, pw, pw, (rocblas_int)mp,
+                                                &one, w.Vm, (rocblas_int)mp, mp * pw, w.Vm,
+                                                (rocblas_int)mp, mp * pw, &zero, w.G, pw, nn, B));
+            launch_panel_tinv(w.G, w.tau + p0, s, w.Tinv, pw, B, st);
+            RBCHK(rocblas_dtrsm_strided_batched(rb, rocblas_side_left, rocblas_fill_upper,
+                                                rocblas_operation_none, rocblas_diagonal_non_unit,
+                                                pw, pw, &one, w.Tinv, pw, nn, w.T, pw, nn, B));
+            // C <- (I - V T V^T)^T C = C - V T^T (V^T C) for the trailing columns C
+            double* C = panel + (int64_t)pw * rows;
+            RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_transpose,
+                                                rocblas_operation_none, pw, rest, (rocblas_int)mp,
+                                                &one, w.Vm, (rocblas_int)mp, mp * pw, C,
+                                                (rocblas_int)rows, strideA, &zero, w.W2, pw,
+                                                (int64_t)pw * rest, B));
+            RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_transpose,
+                                                rocblas_operation_none, pw, rest, pw, &one, w.T,
+                                                pw, nn, w.W2, pw, (int64_t)pw * rest, &zero, w.W3,
+                                                pw, (int64_t)pw * rest, B));
+            RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_none, rocblas_operation_none,
+                                                (rocblas_int)mp, rest, pw, &mone, w.Vm,
+                                                (rocblas_int)mp, mp * pw, w.W3, pw,
+                                                (int64_t)pw * rest, &one, C, (rocblas_int)rows,
+                                                strideA, B));
+        }
+    }
+
+    void orthq(double* Y, int64_t rows, int s, double* Q, double* R, const QrWork& w, int B, Carver& cv) {
+        const double one = 1.0, zero = 0.0, mone = -1.0;
+        const rocblas_int ir = (rocblas_int)rows, is = s;
+        const int64_t ss = (int64_t)s * s;
+        tock("r.pre-orth");
+        house_qr(Y, rows, s, w, B);
+        tock(s <= 64 ? "q.house<=64" : "q.house>64");
+        std::vector<QrItem> qi(B);
+        for (int b = 0; b < B; ++b)
+            qi[b] = QrItem{Y + b * rows * s, w.tau + (int64_t)b * s, w.Vm + b * rows * s,
+                           R ? R + b * ss : nullptr, w.G + b * ss, w.Tinv + b * ss, w.T + b * ss,
+                           Q + b * rows * s, rows};
+        QrItem* dq = meta(qi, cv);
+        launch_qr_extract(dq, B, rows, s, st);
+        RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_transpose, rocblas_operation_none,
+                                            is, is, ir, &one, w.Vm, ir, rows * s, w.Vm, ir, rows * s,
+                                            &zero, w.G, is, ss, B));
+        launch_qr_tinv(dq, B, s, st);
+        RBCHK(rocblas_dtrsm_strided_batched(rb, rocblas_side_left, rocblas_fill_upper,
+                                            rocblas_operation_none, rocblas_diagonal_non_unit, is, is,
+                                            &one, w.Tinv, is, ss, w.T, is, ss, B));
+        RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_none, rocblas_operation_transpose,
+                                            is, is, is, &one, w.T, is, ss, w.Vm, ir, rows * s, &zero,
+                                            w.W, is, ss, B));
+        RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_none, rocblas_operation_none, ir,
+                                            is, is, &mone, w.Vm, ir, rows * s, w.W, is, ss, &one, Q,
+                                            ir, rows * s, B));
+    }
+
+    // SVD of the s x s factors R (column-major, stride s^2): A <- U S, J <- V,
+    // sigma decreasing. Jacobi in LDS up to 64; wider sketches use rocSOLVER on
+    // the square matrices (a non-converged item is retried alone in place mode).
+    void small_svd(double* R, double* J, double* S, int B, int s, Carver& cv) {
+        const int64_t ss = (int64_t)s * s;
+        std::vector<JacItem> ji(B);
+        for (int b = 0; b < B; ++b) ji[b] = JacItem{R + b * ss, J + b * ss, S + (int64_t)b * s};
+        JacItem* dj = meta(ji, cv);
+        if (s <= 64) {
+            launch_jacobi(dj, B, s, st);
+            tock("c.jacobi");
+            return;
+        }
+        if (s <= 128) {
+            launch_jacobi128(dj, B, s, st);
+            tock("c.jacobi128");
+            return;
+        }
+        double* Rc = cv.take<double>((size_t)B * ss);
+        double* Ug = cv.take<double>((size_t)B * ss);
+        double* Vg = cv.take<double>((size_t)B * ss);
+        double* Eg = cv.take<double>((size_t)B * s);
+        rocblas_int* inf = cv.take<rocblas_int>(B);
+        HIPCHK(hipMemcpy(Rc, R, (size_t)B * ss * 8, hipMemcpyDeviceToDevice));
+        RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_singular, s,
+                                               s, Rc, s, ss, S, s, Ug, s, ss, Vg, s, ss, Eg, s,
+                                               rocblas_outofplace, inf, B));
+        std::vector<rocblas_int> hi(B);
+        HIPCHK(hipMemcpy(hi.data(), inf, B * sizeof(rocblas_int), hipMemcpyDeviceToHost));
+        for (int b = 0; b < B; ++b) {
+            if (!hi[b]) continue;
+            HIPCHK(hipMemcpy(Rc + b * ss, R + b * ss, ss * 8, hipMemcpyDeviceToDevice));
+            RBCHK(rocsolver_dgesvd(rb, rocblas_svect_singular, rocblas_svect_singular, s, s,
+                                   Rc + b * ss, s, S + (int64_t)b * s, Ug + b * ss, s, Vg + b * ss,
+                                   s, Eg + (int64_t)b * s, rocblas_inplace, inf + b));
+            rocblas_int v = 0;
+            HIPCHK(hipMemcpy(&v, inf + b, sizeof(v), hipMemcpyDeviceToHost));
+            if (v) fail(HH_EINTERNAL, "SVD of a sketch core did not converge");
+        }
+        launch_svd_to_jac(dj, Ug, Vg, B, s, st);
+        tock("c.gesvd>64");
     }
 
     // One randomized round for a batch sharing sketch width s; returns the
     // blocks that need a wider sketch.
     std::vector<int64_t> random_batch(const std::vector<int64_t>& idx, int s, int round) {
         const int B = (int)idx.size();
+        if (verbose()) {
+            tsum["n.items s=" + std::to_string(s)] += B;
+            tsum["n.batches s=" + std::to_string(s)] += 1;
+        }
         int64_t M = 0, N = 0;
         for (int64_t i : idx) {
             M = std::max<int64_t>(M, h->blocks[i].b.ie - h->blocks[i].b.ib);
             N = std::max<int64_t>(N, h->blocks[i].b.je - h->blocks[i].b.jb);
         }
         const int64_t nch = (M * N + SUM_CHUNK - 1) / SUM_CHUNK;
+        const int64_t ss = (int64_t)s * s;
         Carver cv{scratch, scratch_bytes};
         double* H = cv.take<double>((size_t)B * M * N);
         double* Om = cv.take<double>((size_t)B * N * s);
@@ -329,18 +506,13 @@ struct Builder {
         double* Q = cv.take<double>((size_t)B * M * s);
         double* Z = cv.take<double>((size_t)B * N * s);
         double* Q2 = cv.take<double>((size_t)B * N * s);
-        double* Bm = cv.take<double>((size_t)B * s * N);
-        double* Ub = cv.take<double>((size_t)B * s * s);
-        double* Vt = cv.take<double>((size_t)B * s * N);
+        double* R = cv.take<double>((size_t)B * ss);
+        double* J = cv.take<double>((size_t)B * ss);
         double* S = cv.take<double>((size_t)B * s);
-        double* E = cv.take<double>((size_t)B * s);
-        double* S2 = cv.take<double>((size_t)B * s);
-        double* E2 = cv.take<double>((size_t)B * s);
         double* nrm = cv.take<double>(B);
         double* e2 = cv.take<double>(B);
         double* part = cv.take<double>((size_t)B * nch);
-        double* dummy = cv.take<double>(16);
-        rocblas_int* info = cv.take<rocblas_int>(4 * B);   // one slot per SVD call
+        QrWork qw = qr_work(cv, B, std::max(M, N), s);
         std::vector<GenItem> gi(B);
         std::vector<SumItem> si(B);
         std::vector<SketchItem> ski(B);
@@ -350,32 +522,43 @@ struct Builder {
             si[b] = SumItem{H + (int64_t)b * M * N, M * N};
             ski[b] = SketchItem{Om + (int64_t)b * N * s, k.je - k.jb, idx[b], round, 0};
         }
+        tick();
         SumItem* dsi = meta(si, cv);
         launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, meta(gi, cv), B, M, N, M * N, st);
         launch_sumsq(dsi, B, M * N, part, SUM_CHUNK, nrm, st);
         launch_sketch(meta(ski, cv), B, N, s, h->opt.seed, st);
+        tock("r.gen");
         const double one = 1.0, zero = 0.0, mone = -1.0;
         const rocblas_operation NT = rocblas_operation_none, TR = rocblas_operation_transpose;
         const rocblas_int iM = (rocblas_int)M, iN = (rocblas_int)N, is = s;
-        // range finder with one power iteration
+        // range finder with one power iteration: Q = orth(H orth(H^T orth(H Omega)))
         RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, iN, &one, H, iM, M * N, Om, iN,
                                             N * s, &zero, Y, iM, M * s, B));
-        orth(Y, M, s, Q, S2, E2, dummy, info + B, B);
+        tock("r.gemm");
+        orthq(Y, M, s, Q, nullptr, qw, B, cv);
+        tock("r.orth");
         RBCHK(rocblas_dgemm_strided_batched(rb, TR, NT, iN, is, iM, &one, H, iM, M * N, Q, iM,
                                             M * s, &zero, Z, iN, N * s, B));
-        orth(Z, N, s, Q2, S2, E2, dummy, info + 2 * B, B);
+        tock("r.gemm");
+        orthq(Z, N, s, Q2, nullptr, qw, B, cv);
+        tock("r.orth");
         RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, iN, &one, H, iM, M * N, Q2, iN,
                                             N * s, &zero, Y, iM, M * s, B));
-        orth(Y, M, s, Q, S2, E2, dummy, info + 3 * B, B);
-        // B = Q^T H, then H <- H - Q B and its Frobenius norm (the discarded part)
-        RBCHK(rocblas_dgemm_strided_batched(rb, TR, NT, is, iN, iM, &one, Q, iM, M * s, H, iM,
-                                            M * N, &zero, Bm, is, s * N, B));
-        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, iN, is, &mone, Q, iM, M * s, Bm, is,
-                                            s * N, &one, H, iM, M * N, B));
+        tock("r.gemm");
+        orthq(Y, M, s, Q, nullptr, qw, B, cv);
+        tock("r.orth");
+        // B^T = H^T Q; H <- H - Q B and its Frobenius norm (the part Q misses)
+        RBCHK(rocblas_dgemm_strided_batched(rb, TR, NT, iN, is, iM, &one, H, iM, M * N, Q, iM,
+                                            M * s, &zero, Z, iN, N * s, B));
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, TR, iM, iN, is, &mone, Q, iM, M * s, Z, iN,
+                                            N * s, &one, H, iM, M * N, B));
         launch_sumsq(dsi, B, M * N, part, SUM_CHUNK, e2, st);
-        RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_singular,
-                                               is, iN, Bm, is, s * N, S, s, Ub, is, s * s, Vt, is,
-                                               s * N, E, s, rocblas_outofplace, info, B));
+        tock("r.gemm");
+        // SVD of B through B^T = Qb R: R = W S J^T gives B = J S (Qb W)^T
+        orthq(Z, N, s, Q2, R, qw, B, cv);
+        tock("r.orth");
+        small_svd(R, J, S, B, s, cv);
+        tock("r.coresvd");
         std::vector<RankItem> ri(B);
         for (int b = 0; b < B; ++b) {
             const Blk& k = h->blocks[idx[b]].b;
@@ -391,12 +574,13 @@ struct Builder {
         }
         RankItem* dri = meta(ri, cv);
         launch_rank(dri, B, eps2, st);
-        // U = Q Ub for every item (only accepted ones are kept)
-        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, is, &one, Q, iM, M * s, Ub, is,
-                                            s * s, &zero, Y, iM, M * s, B));
+        // U = Q J (M x s), V = Qb (W S) (N x s); only accepted items are kept
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iM, is, is, &one, Q, iM, M * s, J, is, ss,
+                                            &zero, Y, iM, M * s, B));
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, iN, is, is, &one, Q2, iN, N * s, R, is, ss,
+                                            &zero, Z, iN, N * s, B));
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpy(ri.data(), dri, B * sizeof(RankItem), hipMemcpyDeviceToHost));
-        check_info(info, 4 * B);
         std::vector<int64_t> acc_idx, retry;
         std::vector<int> acc_rank, acc_pos;
         for (int b = 0; b < B; ++b) {
@@ -418,14 +602,15 @@ struct Builder {
                 if (!acc_rank[a]) continue;
                 FinItem f{};
                 f.U = Y + (int64_t)b * M * s;
-                f.Vt = Vt + (int64_t)b * s * N;
+                f.V = Z + (int64_t)b * N * s;
+                f.v_rows = 0;
                 f.sigma = S + (int64_t)b * s;
                 f.Uout = (double*)r.u_ptr;
                 f.Vout = (double*)r.v_ptr;
                 f.ib = r.b.ib;
                 f.jb = r.b.jb;
                 f.ldu = M;
-                f.ldv = s;
+                f.ldv = N;
                 f.PI = r.PI;
                 f.PJ = r.PJ;
                 f.m = (int)(r.b.ie - r.b.ib);
@@ -437,6 +622,7 @@ struct Builder {
             HIPCHK(hipGetLastError());
         }
         HIPCHK(hipDeviceSynchronize());
+        tock("r.rank+fin");
         return retry;
     }
 
@@ -445,8 +631,9 @@ struct Builder {
         return 8 * (size_t)(M * N + M * p + p * N + 2 * p + 2 + (M * N) / SUM_CHUNK + 1) + 1024;
     }
     size_t random_item_bytes(int64_t M, int64_t N, int64_t s) const {
-        return 8 * (size_t)(M * N + 2 * N * s + 2 * M * s + 2 * N * s + s * s + 2 * s * N +
-                            4 * s + 3 + (M * N) / SUM_CHUNK + 1) + 2048;
+        const int64_t mx = std::max(M, N);
+        return 8 * (size_t)(M * N + 3 * N * s + 2 * M * s + mx * s + 10 * s * s + 64 * s + 4 * s + 3 +
+                            (M * N) / SUM_CHUNK + 1) + 8192;
     }
 
     // Size bucket: dimensions within a factor 2^(1/4) share a bucket, so zero
@@ -491,8 +678,12 @@ struct Builder {
             const Blk& k = h->blocks[i].b;
             (std::min(k.ie - k.ib, k.je - k.jb) <= EXACT_SVD_MAX ? exact : rnd).push_back(i);
         }
+        total_cand = (int64_t)cand.size();
         batched(exact, [&](int64_t M, int64_t N) { return exact_item_bytes(M, N); },
-                [&](const std::vector<int64_t>& b) { exact_batch(b); });
+                [&](const std::vector<int64_t>& b) {
+                    exact_batch(b);
+                    progress((int64_t)b.size(), "exact SVD");
+                });
         // randomized: groups keyed by sketch width, widening on demand
         std::map<int, std::vector<int64_t>> queue;
         std::map<int64_t, int> rounds;
@@ -514,7 +705,9 @@ struct Builder {
                 batched(kv.second,
                         [&](int64_t M, int64_t N) { return random_item_bytes(M, N, s); },
                         [&](const std::vector<int64_t>& b) {
-                            for (int64_t r : random_batch(b, s, round)) {
+                            auto again = random_batch(b, s, round);
+                            progress((int64_t)(b.size() - again.size()), "randomized");
+                            for (int64_t r : again) {
                                 const Blk& k = h->blocks[r].b;
                                 int pmin = (int)std::min(k.ie - k.ib, k.je - k.jb);
                                 int s2 = std::min(2 * s, pmin);
@@ -525,6 +718,8 @@ struct Builder {
                         });
             }
         }
+        progress(0, "done", true);
+        report_times();
     }
 
     // Dense blocks generated in place (padded-row layout) and their norms.
@@ -576,7 +771,7 @@ struct Builder {
     }
 
     // Alg. 3 storage: round every low-rank factor into its format's arena.
-    void pack() {
+    void pack(bool in_place_ok = true) {
         int64_t need[4] = {0, 0, 0, 0};
         std::vector<int64_t> lr;
         for (size_t i = 0; i < h->blocks.size(); ++i) {
@@ -588,7 +783,7 @@ struct Builder {
         }
         bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0;
         h->all_fp64 = all64;
-        if (all64) return;   // the fp64 store already is the arena
+        if (all64 && in_place_ok) return;   // the fp64 store already is the arena
         // exponents of the scaled formats
         std::vector<double> mx(2 * lr.size(), 0.0);
         {
@@ -834,6 +1029,19 @@ static void fill_stats(hh_handle* h, double seconds) {
         }
     }
     const double io = h->opt.io_dtype == HH_IO_F32 ? 4.0 : 8.0;
+    double vb = 0, ub = 0, db = 0;
+    for (const auto& r : h->blocks) {
+        const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
+        if (r.lowrank) {
+            vb += (double)r.rank * n * fmt_size(r.fmt);
+            ub += (double)r.rank * m * fmt_size(r.fmt);
+        } else {
+            db += 8.0 * m * n;
+        }
+    }
+    s.phase_bytes[0] = (io + 8.0) * h->plan.n;
+    s.phase_bytes[1] = vb;
+    s.phase_bytes[2] = ub + db + io * h->plan.n;
     s.storage_words = words;
     s.storage_words_fp64 = words64;
     s.matvec_bytes = bytes + 2.0 * io * h->plan.n;
@@ -957,9 +1165,70 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
 }  // namespace hh
 
 namespace hh {
+// A handle with the source's tree, partition and fp64 factors re-stored under
+// new options (Alg. 3 with another precision set, or uniform fp64).
 hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
-    (void)src;
-    (void)opt;
-    fail(HH_ENOTSUP, "hh_derive is not available yet");
+    auto t0 = std::chrono::steady_clock::now();
+    hh_options o{};
+    o.precision_mask = 0xF;
+    if (opt) o = *opt;
+    if (o.precision_mask == 0) o.precision_mask = 0xF;
+    if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
+    if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
+    if (!src->all_fp64) fail(HH_ENOTSUP, "hh_derive needs a source whose factors are all fp64");
+    for (const auto& r : src->blocks)
+        if (r.b.kind == HH_BLK_DENSE_NEAR)
+            fail(HH_ENOTSUP, "hh_derive does not support sources with ell == L");
+    std::unique_ptr<hh_handle> h(new hh_handle());
+    h->plan = src->plan;
+    h->device = src->device;
+    h->kd = src->kd;
+    h->tol = src->tol;
+    h->opt = o;
+    h->np = src->np;
+    h->leaf_poff = src->leaf_poff;
+    h->leaf_psz = src->leaf_psz;
+    h->tpad = src->tpad;
+    h->blocks = src->blocks;
+    h->d_tpad = upload(h->mem, h->tpad);
+    {
+        std::vector<int64_t> pmap(h->np, -1);
+        for (int64_t t = 0; t < h->plan.n; ++t) pmap[h->tpad[t]] = h->plan.perm[t];
+        h->d_pmap = upload(h->mem, pmap);
+    }
+    // dense blocks: own copy
+    int64_t total = 0;
+    for (const auto& r : h->blocks)
+        if (!r.lowrank) total += r.PI * (r.b.je - r.b.jb);
+    double* D = static_cast<double*>(h->mem.alloc((size_t)total * 8 + 256, false));
+    int64_t off = 0;
+    for (auto& r : h->blocks) {
+        if (r.lowrank) continue;
+        const int64_t cnt = r.PI * (r.b.je - r.b.jb);
+        HIPCHK(hipMemcpy(D + off, r.d_ptr, (size_t)cnt * 8, hipMemcpyDeviceToDevice));
+        r.d_ptr = D + off;
+        off += cnt;
+    }
+    const bool uniform = o.uniform_fp64 != 0;
+    double total2 = 0.0;
+    for (const auto& r : h->blocks) total2 += r.lowrank ? r.nb2 : r.entry2;
+    for (auto& r : h->blocks) {
+        if (!r.lowrank) continue;
+        int fmt = HH_FMT_FP64;
+        if (!uniform) choose_lowrank_format(r, total2, h->plan.d, h->tol, o.precision_mask, fmt);
+        r.fmt = fmt;
+        r.eU = r.eV = 0;
+    }
+    Builder B(h.get());
+    B.init((size_t)256 << 20);
+    B.pack(false);              // reads the source's fp64 factors, writes own arenas
+    build_tasks(h.get());
+    h->ws_R = 1;
+    h->xt = static_cast<double*>(h->mem.alloc((size_t)h->np * 8 + 256, true));
+    h->tb = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->ncols, 1) * 8 + 256, true));
+    HIPCHK(hipDeviceSynchronize());
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(h.get(), secs);
+    return h.release();
 }
 }  // namespace hh

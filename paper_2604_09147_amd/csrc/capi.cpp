@@ -48,7 +48,7 @@ static void check_device(const hh_handle* h) {
 }
 
 static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, void* stream,
-                    bool trans) {
+                    bool trans, double* phase_ms = nullptr) {
     if (!hc) fail(HH_EINVAL, "handle is NULL");
     if (!x || !y) fail(HH_EINVAL, "x and y must be device pointers");
     if (x == y) fail(HH_EINVAL, "x and y must not alias");
@@ -59,10 +59,27 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     Desc d{h->xt, h->tb, h->d_pmap, x, y, h->np, h->opt.io_dtype, 0};
     const int R = (int)nrhs;
     const TaskSet& S = trans ? h->bwd : h->fwd;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (phase_ms) {
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventRecord(ev[0], (hipStream_t)stream));
+    }
     launch_gather(d, nullptr, 1, h->np, R, stream);
+    if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
     launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
+    if (phase_ms) HIPCHK(hipEventRecord(ev[2], (hipStream_t)stream));
     launch_axpy(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), S.d_runs, S.d_druns, R, stream);
     HIPCHK(hipGetLastError());
+    if (phase_ms) {
+        HIPCHK(hipEventRecord(ev[3], (hipStream_t)stream));
+        HIPCHK(hipEventSynchronize(ev[3]));
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            phase_ms[k] = ms;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    }
 }
 
 static void product_batch(const hh_handle* const* hs, int count, const void* const* x,
@@ -186,6 +203,14 @@ hh_status hh_matvec(const hh_handle* h, const void* x, void* y, int64_t nrhs, vo
 hh_status hh_matvec_t(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream) {
     GUARD_BEGIN
     product(h, x, y, nrhs, stream, true);
+    GUARD_END
+}
+
+hh_status hh_matvec_timed(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream,
+                          int trans, double* phase_ms) {
+    GUARD_BEGIN
+    if (!phase_ms) fail(HH_EINVAL, "phase_ms is NULL");
+    product(h, x, y, nrhs, stream, trans != 0, phase_ms);
     GUARD_END
 }
 

@@ -55,14 +55,36 @@ struct RankItem {
 
 struct FinItem {
     const double* U;     // m x >= k, column-major, leading dimension ldu
-    const double* Vt;    // >= k x n, column-major, leading dimension ldv (rows = singular index)
+    const double* V;     // right factor: see v_rows
     const double* sigma;
     double* Uout;        // PI x k padded-row layout
     double* Vout;        // PJ x k padded-row layout
     int64_t ib, jb;
     int64_t ldu, ldv;
     int64_t PI, PJ;
-    int32_t m, n, k, pad_;
+    int32_t m, n, k;
+    int32_t v_rows;      // 1: V holds V^T (singular index = row, ld ldv), times sigma;
+                         // 0: V is n x k column-major (ld ldv), already scaled
+};
+
+// Householder QR (geqrf output) -> explicit Q (compact-WY helpers).
+struct QrItem {
+    const double* A;     // rows x s after geqrf (R above, reflectors below)
+    const double* tau;   // s
+    double* Vm;          // rows x s unit lower trapezoidal reflectors (0 column when tau = 0)
+    double* R;           // s x s upper triangle of A, or null
+    double* G;           // s x s, V^T V (input of the T kernel)
+    double* Tinv;        // s x s: diag(1/tau) + strict upper part of G
+    double* T;           // s x s: set to the identity (right-hand side of the solve)
+    double* Q;           // rows x s: set to [I; 0]
+    int64_t rows;
+};
+
+// One-sided Jacobi SVD of a small square matrix.
+struct JacItem {
+    double* A;           // s x s column-major: in A, out A J (columns sigma_r w_r), sorted
+    double* J;           // s x s out: accumulated rotations (right singular vectors)
+    double* sigma;       // s out, decreasing
 };
 
 struct PackItem {
@@ -89,5 +111,18 @@ void launch_rank(RankItem* items, int nitems, double eps2, hipStream_t s);
 void launch_finalize(const FinItem* items, int nitems, const int64_t* tpad, hipStream_t s);
 void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s);
 void launch_pack(const PackItem* items, int nitems, int64_t max_count, hipStream_t s);
+void launch_house_qr(double* A, int64_t ld, int64_t strideA, double* tau, int64_t strideT,
+                     int64_t m, int n, int nitems, hipStream_t st);
+void launch_panel_v(const double* A, int64_t ld, int64_t strideA, const double* tau,
+                    int64_t strideT, double* V, double* T, int64_t m, int nb, int nitems,
+                    hipStream_t st);
+void launch_panel_tinv(const double* G, const double* tau, int64_t strideT, double* Tinv, int nb,
+                       int nitems, hipStream_t st);
+void launch_qr_extract(const QrItem* items, int nitems, int64_t rows, int s, hipStream_t st);
+void launch_qr_tinv(const QrItem* items, int nitems, int s, hipStream_t st);
+void launch_jacobi(const JacItem* items, int nitems, int s, hipStream_t st);
+void launch_jacobi128(const JacItem* items, int nitems, int s, hipStream_t st);
+void launch_svd_to_jac(const JacItem* items, const double* U, const double* Vt, int nitems, int s,
+                       hipStream_t st);
 
 }  // namespace hh

@@ -10,6 +10,13 @@
 
 namespace hh {
 
+static inline unsigned grid_for(int64_t total, int64_t cap = 65535) {
+    int64_t g = (total + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
 // --------------------------------------------------------------- rounding
 // Round-to-nearest-even from float64 straight to the storage format (no
 // detour through fp32, which would round twice).
@@ -219,9 +226,9 @@ __global__ void rank_kernel(RankItem* items, int nitems, double eps2) {
     it.trunc2 = nb2;
 }
 
-// Write U (m x k) and V = W Sigma (n x k) of an accepted item into the fp64
-// store in padded-row layout, after fixing signs so that the largest-|.|
-// entry of each column of U (first index on ties) is positive.
+// Write U (m x k) and V (n x k) of an accepted item into the fp64 store in
+// padded-row layout, after fixing signs so that the largest-|.| entry of each
+// column of U (first index on ties) is positive.
 __global__ void finalize_kernel(const FinItem* items, const int64_t* tpad) {
     __shared__ double bv[256];
     __shared__ int bi[256];
@@ -253,9 +260,422 @@ __global__ void finalize_kernel(const FinItem* items, const int64_t* tpad) {
         for (int i = tid; i < it.m; i += blockDim.x) uo[tpad[it.ib + i] - rb] = sgn * u[i];
         double* vo = it.Vout + (int64_t)r * it.PJ;
         const int64_t cb = tpad[it.jb];
-        const double sr = sgn * it.sigma[r];
-        for (int j = tid; j < it.n; j += blockDim.x)
-            vo[tpad[it.jb + j] - cb] = sr * it.Vt[(int64_t)j * it.ldv + r];
+        if (it.v_rows) {
+            const double sr = sgn * it.sigma[r];
+            for (int j = tid; j < it.n; j += blockDim.x)
+                vo[tpad[it.jb + j] - cb] = sr * it.V[(int64_t)j * it.ldv + r];
+        } else {
+            const double* v = it.V + (int64_t)r * it.ldv;
+            for (int j = tid; j < it.n; j += blockDim.x) vo[tpad[it.jb + j] - cb] = sgn * v[j];
+        }
+    }
+}
+
+// Householder QR of one m x n panel per workgroup (column-major, leading
+// dimension ld, items strideA / strideT apart), in LAPACK geqrf layout: R on
+// and above the diagonal, the reflectors v (v_j = 1 implied) below it, tau[j];
+// A = H_1 ... H_n R with H_j = I - tau_j v v^T. Reflector j follows dlarfg:
+// beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta, v = x / (alpha - beta);
+// tau = 0 when the part below the diagonal is already zero. Trailing columns
+// are updated in chunks of 32 with one block-wide reduction per chunk.
+__global__ __launch_bounds__(256) void house_qr_kernel(double* A, int64_t ld, int64_t strideA,
+                                                       double* tau, int64_t strideT, int64_t m,
+                                                       int n) {
+    __shared__ double red[4][33];
+    __shared__ double bc[33];
+    double* a = A + (int64_t)blockIdx.x * strideA;
+    double* tj = tau + (int64_t)blockIdx.x * strideT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int jmax = (int)(n < m ? n : m);
+    for (int j = 0; j < jmax; ++j) {
+        double* col = a + (int64_t)j * ld;
+        double ss = 0.0;
+        for (int64_t i = j + 1 + tid; i < m; i += 256) ss += col[i] * col[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+        if (lane == 0) red[wave][0] = ss;
+        __syncthreads();
+        const double sigma = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+        const double alpha = col[j];
+        double t = 0.0, beta = alpha, scal = 0.0;
+        if (sigma != 0.0) {
+            const double nrm = sqrt(alpha * alpha + sigma);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        __syncthreads();
+        if (t != 0.0)
+            for (int64_t i = j + 1 + tid; i < m; i += 256) col[i] *= scal;
+        if (tid == 0) {
+            tj[j] = t;
+            col[j] = beta;
+        }
+        __syncthreads();
+        if (t == 0.0) continue;
+        // trailing update: w_c = v^T a_c, a_c -= t v w_c for c = j+1 .. n-1
+        for (int c0 = j + 1; c0 < n; c0 += 32) {
+            const int nc = n - c0 < 32 ? n - c0 : 32;
+            double w[32];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) w[c] = 0.0;
+            for (int64_t i = j + tid; i < m; i += 256) {
+                const double v = i == j ? 1.0 : col[i];
+#pragma unroll
+                for (int c = 0; c < 32; ++c)
+                    if (c < nc) w[c] += v * a[(int64_t)(c0 + c) * ld + i];
+            }
+#pragma unroll
+            for (int c = 0; c < 32; ++c) {
+                double x = w[c];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                if (lane == 0) red[wave][c] = x;
+            }
+            __syncthreads();
+            if (tid < nc) bc[tid] = t * (red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
+            __syncthreads();
+            for (int64_t i = j + tid; i < m; i += 256) {
+                const double v = i == j ? 1.0 : col[i];
+                for (int c = 0; c < nc; ++c) a[(int64_t)(c0 + c) * ld + i] -= v * bc[c];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+void launch_house_qr(double* A, int64_t ld, int64_t strideA, double* tau, int64_t strideT,
+                     int64_t m, int n, int nitems, hipStream_t st) {
+    hipLaunchKernelGGL(house_qr_kernel, dim3(nitems), dim3(256), 0, st, A, ld, strideA, tau,
+                       strideT, m, n);
+}
+
+// Panel reflectors -> unit lower trapezoidal V (m x nb, contiguous, zero column
+// where tau = 0) and the identity in T (nb x nb), for the compact-WY update of
+// the trailing columns in a blocked QR.
+__global__ void panel_v_kernel(const double* A, int64_t ld, int64_t strideA, const double* tau,
+                               int64_t strideT, double* V, double* T, int64_t m, int nb) {
+    const double* a = A + (int64_t)blockIdx.y * strideA;
+    const double* tj = tau + (int64_t)blockIdx.y * strideT;
+    double* v = V + (int64_t)blockIdx.y * m * nb;
+    double* t = T + (int64_t)blockIdx.y * nb * nb;
+    const int64_t total = m * nb;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % m, j = idx / m;
+        double x = i > j ? a[j * ld + i] : (i == j ? 1.0 : 0.0);
+        if (tj[j] == 0.0) x = 0.0;
+        v[idx] = x;
+        if (i < nb) t[i + j * nb] = i == j ? 1.0 : 0.0;
+    }
+}
+
+// Tinv = diag(1/tau) + strict upper part of G for a panel (batch strides).
+__global__ void panel_tinv_kernel(const double* G, const double* tau, int64_t strideT,
+                                  double* Tinv, int nb) {
+    const double* g = G + (int64_t)blockIdx.x * nb * nb;
+    const double* tj = tau + (int64_t)blockIdx.x * strideT;
+    double* ti = Tinv + (int64_t)blockIdx.x * nb * nb;
+    for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
+        const int i = idx % nb, j = idx / nb;
+        double x = 0.0;
+        if (i < j) x = g[idx];
+        else if (i == j) x = tj[j] != 0.0 ? 1.0 / tj[j] : 1.0;
+        ti[idx] = x;
+    }
+}
+
+void launch_panel_v(const double* A, int64_t ld, int64_t strideA, const double* tau,
+                    int64_t strideT, double* V, double* T, int64_t m, int nb, int nitems,
+                    hipStream_t st) {
+    dim3 grid(grid_for(m * nb, 1024), nitems);
+    hipLaunchKernelGGL(panel_v_kernel, grid, dim3(256), 0, st, A, ld, strideA, tau, strideT, V, T,
+                       m, nb);
+}
+
+void launch_panel_tinv(const double* G, const double* tau, int64_t strideT, double* Tinv, int nb,
+                       int nitems, hipStream_t st) {
+    hipLaunchKernelGGL(panel_tinv_kernel, dim3(nitems), dim3(256), 0, st, G, tau, strideT, Tinv, nb);
+}
+
+// geqrf output -> unit lower trapezoidal reflectors Vm (a zero column where
+// tau = 0, i.e. where the reflector is the identity), the R factor, [I; 0]
+// into Q and the identity into T.
+__global__ void qr_extract_kernel(const QrItem* items, int64_t rows, int s) {
+    const QrItem it = items[blockIdx.y];
+    const int64_t total = rows * s;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % rows, j = idx / rows;
+        double v = i > j ? it.A[idx] : (i == j ? 1.0 : 0.0);
+        if (it.tau[j] == 0.0) v = 0.0;
+        it.Vm[idx] = v;
+        it.Q[idx] = i == j ? 1.0 : 0.0;
+        if (i < s) {
+            if (it.R) it.R[i + j * s] = i <= j ? it.A[idx] : 0.0;
+            it.T[i + j * s] = i == j ? 1.0 : 0.0;
+        }
+    }
+}
+
+// T^-1 = diag(1/tau) + strictly upper part of V^T V, so that
+// H_1 ... H_s = I - V T V^T (compact WY form of the reflectors).
+__global__ void qr_tinv_kernel(const QrItem* items, int s) {
+    const QrItem it = items[blockIdx.y];
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < s * s; idx += gridDim.x * blockDim.x) {
+        const int i = idx % s, j = idx / s;
+        double v = 0.0;
+        if (i < j) v = it.G[idx];
+        else if (i == j) v = it.tau[j] != 0.0 ? 1.0 / it.tau[j] : 1.0;
+        it.Tinv[idx] = v;
+    }
+}
+
+// One-sided (Hestenes) Jacobi SVD of an s x s matrix, s <= 64, in LDS.
+// Pairs follow the round-robin (circle) ordering; 8 lanes per pair. Columns of
+// A are rotated until pairwise orthogonal to 1e-15 relative (at most 40
+// sweeps), J accumulates the rotations, and columns are sorted by norm.
+constexpr int JAC_MAX = 64;
+__global__ __launch_bounds__(256) void jacobi_kernel(const JacItem* items, int s) {
+    __shared__ double A[JAC_MAX * JAC_MAX];
+    __shared__ double J[JAC_MAX * JAC_MAX];
+    __shared__ double sig[JAC_MAX];
+    __shared__ int order[JAC_MAX];
+    __shared__ int rotated;
+    const JacItem it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < s * s; i += 256) {
+        A[i] = it.A[i];
+        J[i] = (i % s == i / s) ? 1.0 : 0.0;
+    }
+    const int se = s + (s & 1);          // even number of players (one dummy when s is odd)
+    const int npairs = se / 2;
+    const int pair = tid >> 3, lane8 = tid & 7;
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int r = 0; r < se - 1; ++r) {
+            int p = -1, q = -1;
+            if (pair < npairs) {
+                if (pair == 0) {
+                    p = 0;
+                    q = (r % (se - 1)) + 1;
+                } else {
+                    p = ((pair + r) % (se - 1)) + 1;
+                    q = ((se - 1 - pair + r) % (se - 1)) + 1;
+                }
+                if (p > q) { int t = p; p = q; q = t; }
+            }
+            const bool live = pair < npairs && q < s;
+            double al = 0.0, be = 0.0, ga = 0.0;
+            if (live)
+                for (int i = lane8; i < s; i += 8) {
+                    const double a = A[i + p * s], b = A[i + q * s];
+                    al += a * a;
+                    be += b * b;
+                    ga += a * b;
+                }
+#pragma unroll
+            for (int off = 4; off > 0; off >>= 1) {
+                al += __shfl_xor(al, off, 8);
+                be += __shfl_xor(be, off, 8);
+                ga += __shfl_xor(ga, off, 8);
+            }
+            if (live && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                for (int i = lane8; i < s; i += 8) {
+                    const double a = A[i + p * s], b = A[i + q * s];
+                    A[i + p * s] = c * a - sn * b;
+                    A[i + q * s] = sn * a + c * b;
+                    const double x = J[i + p * s], y = J[i + q * s];
+                    J[i + p * s] = c * x - sn * y;
+                    J[i + q * s] = sn * x + c * y;
+                }
+                if (lane8 == 0) rotated = 1;
+            }
+            __syncthreads();
+        }
+        const int any = rotated;
+        __syncthreads();
+        if (!any) break;
+    }
+    if (tid < s) {
+        double a = 0.0;
+        for (int i = 0; i < s; ++i) a += A[i + tid * s] * A[i + tid * s];
+        sig[tid] = sqrt(a);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = 0; i < s; ++i) order[i] = i;
+        for (int i = 0; i < s; ++i) {      // selection sort, decreasing; ties keep index order
+            int b = i;
+            for (int j = i + 1; j < s; ++j)
+                if (sig[order[j]] > sig[order[b]]) b = j;
+            int t = order[i]; order[i] = order[b]; order[b] = t;
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < s * s; idx += 256) {
+        const int i = idx % s, r = idx / s, c = order[r];
+        it.A[idx] = A[i + c * s];
+        it.J[idx] = J[i + c * s];
+    }
+    if (tid < s) it.sigma[tid] = sig[order[tid]];
+}
+
+// One-sided Jacobi SVD for 64 < s <= 128 with the columns in registers: 512
+// threads form 64 slot pairs of 8 lanes; each lane keeps 16 rows (i = lane +
+// 8 r) of the two columns of A and of J its pair holds. Every step rotates
+// each pair, then the columns move one seat along the round-robin circle
+// (seat 0 fixed) through LDS, so every pair of columns meets once per sweep.
+// Same rotation, stopping rule and sorted output as the s <= 64 kernel.
+__global__ __launch_bounds__(512) void jacobi128_kernel(const JacItem* items, int s) {
+    __shared__ double buf[128 * 128];
+    __shared__ double sig[128];
+    __shared__ int order[128];
+    __shared__ int rotated;
+    const JacItem it = items[blockIdx.x];
+    const int tid = threadIdx.x, g = tid >> 3, l = tid & 7;
+    const int S = s + (s & 1), P = S / 2;
+    const bool active = g < P;
+    double at[16], ab[16], jt[16], jb[16];
+    {
+        const int ct = g, cb = S - 1 - g;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = l + 8 * r;
+            at[r] = (active && i < s && ct < s) ? it.A[i + ct * s] : 0.0;
+            ab[r] = (active && i < s && cb < s) ? it.A[i + cb * s] : 0.0;
+            jt[r] = (active && i == ct && ct < s) ? 1.0 : 0.0;
+            jb[r] = (active && i == cb && cb < s) ? 1.0 : 0.0;
+        }
+    }
+    // seat that feeds my top / bottom slot after a step (slot index 2g = top, 2g+1 = bottom)
+    const int src_top = g == 0 ? 0 : (g == 1 ? 1 : 2 * (g - 1));
+    const int src_bot = g == P - 1 ? 2 * (P - 1) : 2 * (g + 1) + 1;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int step = 0; step < S - 1; ++step) {
+            double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                al += at[r] * at[r];
+                be += ab[r] * ab[r];
+                ga += at[r] * ab[r];
+            }
+#pragma unroll
+            for (int off = 4; off > 0; off >>= 1) {
+                al += __shfl_xor(al, off, 8);
+                be += __shfl_xor(be, off, 8);
+                ga += __shfl_xor(ga, off, 8);
+            }
+            if (active && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const double a = at[r], b = ab[r];
+                    at[r] = c * a - sn * b;
+                    ab[r] = sn * a + c * b;
+                    const double x = jt[r], y = jb[r];
+                    jt[r] = c * x - sn * y;
+                    jb[r] = sn * x + c * y;
+                }
+                if (l == 0) rotated = 1;
+            }
+            // move the columns one seat along the circle
+            if (active)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    buf[(2 * g) * 128 + l + 8 * r] = at[r];
+                    buf[(2 * g + 1) * 128 + l + 8 * r] = ab[r];
+                }
+            __syncthreads();
+            if (active)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    at[r] = buf[src_top * 128 + l + 8 * r];
+                    ab[r] = buf[src_bot * 128 + l + 8 * r];
+                }
+            __syncthreads();
+            if (active)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    buf[(2 * g) * 128 + l + 8 * r] = jt[r];
+                    buf[(2 * g + 1) * 128 + l + 8 * r] = jb[r];
+                }
+            __syncthreads();
+            if (active)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    jt[r] = buf[src_top * 128 + l + 8 * r];
+                    jb[r] = buf[src_bot * 128 + l + 8 * r];
+                }
+            __syncthreads();
+        }
+        const int any = rotated;
+        __syncthreads();
+        if (!any) break;
+    }
+    // norms per slot, rank of each slot by decreasing norm (ties: lower slot first)
+    if (active)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            buf[(2 * g) * 128 + l + 8 * r] = at[r];
+            buf[(2 * g + 1) * 128 + l + 8 * r] = ab[r];
+        }
+    __syncthreads();
+    if (tid < S) {
+        double a = 0.0;
+        for (int i = 0; i < s; ++i) a += buf[tid * 128 + i] * buf[tid * 128 + i];
+        sig[tid] = sqrt(a);
+    }
+    __syncthreads();
+    if (tid < S) {
+        int rank = 0;
+        for (int u = 0; u < S; ++u)
+            if (sig[u] > sig[tid] || (sig[u] == sig[tid] && u < tid)) ++rank;
+        order[rank] = tid;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < s * s; idx += 512) {
+        const int i = idx % s, r = idx / s;
+        it.A[idx] = buf[order[r] * 128 + i];
+    }
+    if (tid < s) it.sigma[tid] = sig[order[tid]];
+    __syncthreads();
+    if (active)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            buf[(2 * g) * 128 + l + 8 * r] = jt[r];
+            buf[(2 * g + 1) * 128 + l + 8 * r] = jb[r];
+        }
+    __syncthreads();
+    for (int idx = tid; idx < s * s; idx += 512) {
+        const int i = idx % s, r = idx / s;
+        it.J[idx] = buf[order[r] * 128 + i];
+    }
+}
+
+void launch_jacobi128(const JacItem* items, int nitems, int s, hipStream_t st) {
+    hipLaunchKernelGGL(jacobi128_kernel, dim3(nitems), dim3(512), 0, st, items, s);
+}
+
+// rocSOLVER SVD R = U S V^T of a square s x s matrix -> the Jacobi outputs:
+// A <- U S (columns sigma_r u_r), J <- V.
+__global__ void svd_to_jac_kernel(const JacItem* items, const double* U, const double* Vt, int s) {
+    const JacItem it = items[blockIdx.y];
+    const double* u = U + (int64_t)blockIdx.y * s * s;
+    const double* vt = Vt + (int64_t)blockIdx.y * s * s;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < s * s; idx += gridDim.x * blockDim.x) {
+        const int i = idx % s, r = idx / s;
+        it.A[idx] = u[idx] * it.sigma[r];
+        it.J[idx] = vt[r + i * s];
     }
 }
 
@@ -291,12 +711,6 @@ __global__ void pack_kernel(const PackItem* items) {
 }
 
 // ------------------------------------------------------------ launchers
-static inline unsigned grid_for(int64_t total, int64_t cap = 65535) {
-    int64_t g = (total + 255) / 256;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (unsigned)g;
-}
 
 void launch_gen(const KernelDev& k, const double* pts, const double* nrm, const int64_t* tpad,
                 const GenItem* items, int nitems, int64_t M, int64_t N, int64_t max_total,
@@ -327,6 +741,26 @@ void launch_rank(RankItem* items, int nitems, double eps2, hipStream_t s) {
 
 void launch_finalize(const FinItem* items, int nitems, const int64_t* tpad, hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel, dim3(nitems), dim3(256), 0, s, items, tpad);
+}
+
+void launch_qr_extract(const QrItem* items, int nitems, int64_t rows, int s, hipStream_t st) {
+    dim3 grid(grid_for(rows * s, 1024), nitems);
+    hipLaunchKernelGGL(qr_extract_kernel, grid, dim3(256), 0, st, items, rows, s);
+}
+
+void launch_qr_tinv(const QrItem* items, int nitems, int s, hipStream_t st) {
+    dim3 grid(grid_for((int64_t)s * s, 64), nitems);
+    hipLaunchKernelGGL(qr_tinv_kernel, grid, dim3(256), 0, st, items, s);
+}
+
+void launch_jacobi(const JacItem* items, int nitems, int s, hipStream_t st) {
+    hipLaunchKernelGGL(jacobi_kernel, dim3(nitems), dim3(256), 0, st, items, s);
+}
+
+void launch_svd_to_jac(const JacItem* items, const double* U, const double* Vt, int nitems, int s,
+                       hipStream_t st) {
+    dim3 grid(grid_for((int64_t)s * s, 64), nitems);
+    hipLaunchKernelGGL(svd_to_jac_kernel, grid, dim3(256), 0, st, items, U, Vt, s);
 }
 
 void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s) {

@@ -21,7 +21,8 @@ IO_F64, IO_F32 = 0, 1
 BLK_FAR, BLK_NEAR, BLK_WEAK, BLK_DIAG, BLK_DENSE_NEAR = range(5)
 
 # Exported functions, in the order include/hh.h declares them.
-EXPORTS = ["hh_build", "hh_derive", "hh_matvec", "hh_matvec_t", "hh_matvec_batch", "hh_reserve",
+EXPORTS = ["hh_build", "hh_derive", "hh_matvec", "hh_matvec_t", "hh_matvec_timed",
+           "hh_matvec_batch", "hh_reserve",
            "hh_get_stats", "hh_block_count", "hh_get_block", "hh_get_block_factors",
            "hh_get_perm", "hh_io_dtype", "hh_size", "hh_free", "hh_plan_create", "hh_plan_info",
            "hh_plan_blocks", "hh_plan_perm", "hh_plan_free", "hh_quantize", "hh_last_error"]
@@ -52,7 +53,8 @@ class Stats(C.Structure):
                 ("lowrank_entries", C.c_int64), ("dense_entries", C.c_int64),
                 ("total_columns", C.c_int64), ("storage_words", C.c_double),
                 ("storage_words_fp64", C.c_double), ("matvec_bytes", C.c_double),
-                ("norm2_total", C.c_double), ("build_seconds", C.c_double)]
+                ("norm2_total", C.c_double), ("build_seconds", C.c_double),
+                ("phase_bytes", C.c_double * 3)]
 
     def to_dict(self) -> dict:
         out = {}
@@ -93,6 +95,7 @@ def lib() -> C.CDLL:
         "hh_derive": ([_P, C.POINTER(Options), C.POINTER(_P)], C.c_int),
         "hh_matvec": ([_P, _P, _P, C.c_int64, _P], C.c_int),
         "hh_matvec_t": ([_P, _P, _P, C.c_int64, _P], C.c_int),
+        "hh_matvec_timed": ([_P, _P, _P, C.c_int64, _P, C.c_int, _DP], C.c_int),
         "hh_matvec_batch": ([C.POINTER(_P), C.c_int, C.POINTER(_P), C.POINTER(_P), C.c_int64, _P],
                             C.c_int),
         "hh_reserve": ([_P, C.c_int64], C.c_int),
@@ -247,6 +250,14 @@ class HMatrix:
         _check(lib().hh_matvec_t(self._h, C.c_void_p(xc.data_ptr()), C.c_void_p(y.data_ptr()),
                                  nrhs, _stream_ptr(stream)))
         return y
+
+    def matvec_timed(self, x, out=None, stream=None, trans=False):
+        """One product with HIP events around its kernels: (y, [gather, dot, axpy] ms)."""
+        xc, y, nrhs = self._prep(x, out)
+        ms = np.zeros(3)
+        _check(lib().hh_matvec_timed(self._h, C.c_void_p(xc.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     nrhs, _stream_ptr(stream), int(bool(trans)), _dptr(ms)))
+        return y, ms
 
     def reserve(self, max_nrhs: int) -> None:
         _check(lib().hh_reserve(self._h, int(max_nrhs)))

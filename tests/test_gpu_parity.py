@@ -153,3 +153,17 @@ def test_products_are_bitwise_reproducible():
     assert np.array_equal(y1, y2)
     X = torch.randn(2500, 3, dtype=torch.float64, device="cuda")
     assert np.array_equal(g.matvec_t(X).cpu().numpy(), g.matvec_t(X).cpu().numpy())
+
+
+def test_wide_sketches_high_rank_blocks():
+    # 1024-point sibling blocks of a 3D 1/r matrix at tol 1e-8 have ranks above 112,
+    # so the sketch widens to 128 / 256 / 512 (blocked QR, register Jacobi, wide SVD)
+    rng = np.random.default_rng(31)
+    P = rng.random((8192, 3))
+    tol = 1e-8
+    g, o = build_pair(P, W.INV_R, tol, 1.5, 0, 1024, seed=5)
+    sk = {sb.comp.sketch for sb in o.blocks if sb.comp is not None}
+    assert max(sk) >= 256, sk
+    compare_structure(g, o)
+    _check_products(g, o, P, O.Kernel(W.INV_R), tol, dense=False)
+    _check_products(g, o, P, O.Kernel(W.INV_R), tol, trans=True, dense=False)

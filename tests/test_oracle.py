@@ -236,8 +236,9 @@ def _block(m, n, seed=0, kind=W.INV_R, d=3, gap=1.0):
 @pytest.mark.parametrize("eps", [1e-2, 1e-6, 1e-10])
 def test_exact_compression_rank_is_minimal(eps):
     # Eckart-Young with an independent LAPACK driver: the rank-(k-1) optimum misses eps
-    H = _block(200, 150, 1, gap=0.2)
+    H = _block(60, 50, 1, gap=0.2)
     c = O.compress(H, eps)
+    assert c.sketch == 0
     s = scipy.linalg.svd(H, compute_uv=False, lapack_driver="gesvd")
     nrm = np.linalg.norm(H)
     err = np.linalg.norm(H - c.U @ c.V.T)
@@ -246,10 +247,12 @@ def test_exact_compression_rank_is_minimal(eps):
     assert np.allclose(c.U.T @ c.U, np.eye(c.rank), atol=1e-12)
 
 
-@pytest.mark.parametrize("eps", [1e-4, 1e-8])
-def test_randomized_compression_matches_exact_rank(eps):
-    # large block (min(m, n) > 512): certified bound holds and the rank equals the SVD rank
-    H = _block(700, 640, 2, gap=0.5)
+@pytest.mark.parametrize("eps,m,n", [(1e-4, 700, 640), (1e-8, 700, 640), (1e-6, 200, 150),
+                                     (1e-10, 130, 90)])
+def test_randomized_compression_matches_exact_rank(eps, m, n):
+    # block above the exact-SVD size: the certified bound holds and the rank equals
+    # the rank of the exact SVD computed by an independent LAPACK driver
+    H = _block(m, n, 2, gap=0.5)
     c = O.compress(H, eps, seed=9, uid=3)
     assert c.sketch > 0
     nrm2 = float(np.sum(H * H))
