@@ -888,13 +888,17 @@ static void build_tasks(hh_handle* h) {
     h->ncols = col;
     TaskSet& F = h->fwd;
     TaskSet& T = h->bwd;
+    if (h->np >= ((int64_t)1 << 31) || h->ncols >= ((int64_t)1 << 31))
+        fail(HH_ENOTSUP, "padded length and stored columns must stay below 2^31");
     for (const auto& r : h->blocks) {
         if (!(r.lowrank && r.rank > 0)) continue;
         const size_t es = fmt_size(r.fmt);
         for (int pass = 0; pass < 2; ++pass) {
             const int64_t Pl = pass == 0 ? r.PJ : r.PI;
             const char* base = static_cast<const char*>(pass == 0 ? r.v_ptr : r.u_ptr);
-            int64_t cpt = std::max<int64_t>(1, std::min<int64_t>(r.rank, DOT_TASK_ELEMS / std::max<int64_t>(Pl, 1)));
+            // about DOT_TASK_ELEMS elements per task, and a column for each wave
+            const int64_t cpt = std::min<int64_t>(
+                r.rank, std::max<int64_t>(4, DOT_TASK_ELEMS / std::max<int64_t>(Pl, 1)));
             for (int64_t c0 = 0; c0 < r.rank; c0 += cpt) {
                 DotTask t{};
                 t.col0 = base + (size_t)(c0 * Pl) * es;
@@ -908,65 +912,72 @@ static void build_tasks(hh_handle* h) {
             }
         }
     }
-    // blocks by (level, row box) and (level, column box)
-    std::map<std::pair<int, int64_t>, std::vector<int64_t>> by_row, by_col;
-    for (size_t i = 0; i < h->blocks.size(); ++i) {
-        const Blk& b = h->blocks[i].b;
-        by_row[{b.level, b.bi}].push_back((int64_t)i);
-        by_col[{b.level, b.bj}].push_back((int64_t)i);
-    }
+    // clusters in (level, box) order; cluster (l, b) has index
+    // sum_{l' < l} 2^(d l') + b. Blocks join the cluster of their row box
+    // (forward) or column box (transpose), in canonical block order.
+    std::vector<int64_t> first(L + 2, 0);
+    for (int l = 0; l <= L; ++l) first[l + 1] = first[l] + ((int64_t)1 << (d * l));
+    const int64_t ncl = first[L + 1];
     const int64_t nleaf = (int64_t)1 << (d * L);
-    for (int64_t lf = 0; lf < nleaf; ++lf) {
-        if (h->leaf_psz[lf] == 0) continue;
-        for (int dir = 0; dir < 2; ++dir) {
-            TaskSet& S = dir == 0 ? F : T;
+    for (int dir = 0; dir < 2; ++dir) {
+        TaskSet& S = dir == 0 ? F : T;
+        std::vector<std::vector<Run>> per(ncl);
+        std::vector<std::vector<DotRun>> dper(dir == 1 ? nleaf : 0);
+        for (const auto& r : h->blocks) {
+            const int64_t box = dir == 0 ? r.b.bi : r.b.bj;
+            const int64_t ci = first[r.b.level] + box;
+            if (r.lowrank) {
+                if (r.rank == 0) continue;
+                Run rn{};
+                rn.base = dir == 0 ? r.u_ptr : r.v_ptr;
+                rn.pc = dir == 0 ? r.pI : r.pJ;
+                rn.stride = (int32_t)(dir == 0 ? r.PI : r.PJ);
+                rn.toff = (int32_t)r.col;
+                rn.ncols = r.rank;
+                rn.exp = (int16_t)(r.eU + r.eV);
+                rn.fmt = (int8_t)r.fmt;
+                rn.from_x = 0;
+                per[ci].push_back(rn);
+            } else if (dir == 0) {
+                Run rn{};
+                rn.base = r.d_ptr;
+                rn.pc = r.pI;
+                rn.stride = (int32_t)r.PI;
+                rn.toff = (int32_t)r.pJ;
+                rn.ncols = (int32_t)(r.b.je - r.b.jb);
+                rn.exp = 0;
+                rn.fmt = HH_FMT_FP64;
+                rn.from_x = 1;
+                per[ci].push_back(rn);
+            } else {
+                if (r.b.level != L) fail(HH_EINTERNAL, "dense block above the leaf level");
+                DotRun dr{};
+                dr.base = r.d_ptr;
+                dr.xoff = r.pI;
+                dr.P = (int32_t)r.PI;
+                dr.ncols = (int32_t)(r.b.je - r.b.jb);
+                dper[r.b.bj].push_back(dr);
+            }
+        }
+        S.cl_run.assign(ncl + 1, 0);
+        for (int64_t c = 0; c < ncl; ++c) {
+            S.runs.insert(S.runs.end(), per[c].begin(), per[c].end());
+            S.cl_run[c + 1] = (int32_t)S.runs.size();
+        }
+        if (dir == 1) {
+            S.cl_drun.assign(nleaf + 1, 0);
+            for (int64_t b = 0; b < nleaf; ++b) {
+                S.druns.insert(S.druns.end(), dper[b].begin(), dper[b].end());
+                S.cl_drun[b + 1] = (int32_t)S.druns.size();
+            }
+        }
+        for (int64_t lf = 0; lf < nleaf; ++lf) {
+            if (h->leaf_psz[lf] == 0) continue;
             LeafTask lt{};
             lt.poff = h->leaf_poff[lf];
             lt.P = (int32_t)h->leaf_psz[lf];
-            lt.run_begin = (int32_t)S.runs.size();
-            lt.drun_begin = (int32_t)S.druns.size();
-            for (int l = 0; l <= L; ++l) {
-                int64_t anc = lf >> (d * (L - l));
-                auto& mp = dir == 0 ? by_row : by_col;
-                auto it = mp.find({l, anc});
-                if (it == mp.end()) continue;
-                for (int64_t bi : it->second) {
-                    const BlockRec& r = h->blocks[bi];
-                    if (r.lowrank) {
-                        if (r.rank == 0) continue;
-                        const size_t es = fmt_size(r.fmt);
-                        Run rn{};
-                        const int64_t rowoff = dir == 0 ? lt.poff - r.pI : lt.poff - r.pJ;
-                        rn.base = static_cast<const char*>(dir == 0 ? r.u_ptr : r.v_ptr) + (size_t)rowoff * es;
-                        rn.stride = dir == 0 ? r.PI : r.PJ;
-                        rn.toff = r.col;
-                        rn.scale = std::ldexp(1.0, r.eU + r.eV);
-                        rn.ncols = r.rank;
-                        rn.fmt = r.fmt;
-                        rn.from_x = 0;
-                        S.runs.push_back(rn);
-                    } else if (dir == 0) {
-                        Run rn{};
-                        rn.base = r.d_ptr;
-                        rn.stride = r.PI;
-                        rn.toff = r.pJ;
-                        rn.scale = 1.0;
-                        rn.ncols = (int32_t)(r.b.je - r.b.jb);
-                        rn.fmt = HH_FMT_FP64;
-                        rn.from_x = 1;
-                        S.runs.push_back(rn);
-                    } else {
-                        DotRun dr{};
-                        dr.base = r.d_ptr;
-                        dr.xoff = r.pI;
-                        dr.P = (int32_t)r.PI;
-                        dr.ncols = (int32_t)(r.b.je - r.b.jb);
-                        S.druns.push_back(dr);
-                    }
-                }
-            }
-            lt.run_end = (int32_t)S.runs.size();
-            lt.drun_end = (int32_t)S.druns.size();
+            lt.leaf = (int32_t)lf;
+            lt.hid = 0;
             S.leaf.push_back(lt);
         }
     }
@@ -974,7 +985,9 @@ static void build_tasks(hh_handle* h) {
         S->d_dot = upload(h->mem, S->dot);
         S->d_leaf = upload(h->mem, S->leaf);
         S->d_runs = upload(h->mem, S->runs);
-        S->d_druns = upload(h->mem, S->druns);
+        S->d_cl_run = upload(h->mem, S->cl_run);
+        S->d_druns = S->druns.empty() ? nullptr : upload(h->mem, S->druns);
+        S->d_cl_drun = S->cl_drun.empty() ? nullptr : upload(h->mem, S->cl_drun);
     }
 }
 

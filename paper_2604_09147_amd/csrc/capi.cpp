@@ -47,6 +47,24 @@ static void check_device(const hh_handle* h) {
     if (dev != h->device) fail(HH_EINVAL, "the current device is not the handle's device");
 }
 
+static Desc make_desc(const hh_handle* h, const TaskSet& S, const void* x, void* y) {
+    Desc d{};
+    d.xt = h->xt;
+    d.tb = h->tb;
+    d.pmap = h->d_pmap;
+    d.x = x;
+    d.y = y;
+    d.runs = S.d_runs;
+    d.cl_run = S.d_cl_run;
+    d.druns = S.d_druns;
+    d.cl_drun = S.d_cl_drun;
+    d.np = h->np;
+    d.io = h->opt.io_dtype;
+    d.d = h->plan.d;
+    d.L = h->plan.L;
+    return d;
+}
+
 static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, void* stream,
                     bool trans, double* phase_ms = nullptr) {
     if (!hc) fail(HH_EINVAL, "handle is NULL");
@@ -56,9 +74,9 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     check_device(hc);
     hh_handle* h = const_cast<hh_handle*>(hc);
     ensure_workspace(h, nrhs);
-    Desc d{h->xt, h->tb, h->d_pmap, x, y, h->np, h->opt.io_dtype, 0};
     const int R = (int)nrhs;
     const TaskSet& S = trans ? h->bwd : h->fwd;
+    const Desc d = make_desc(h, S, x, y);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (phase_ms) {
         for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -68,7 +86,7 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
     launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[2], (hipStream_t)stream));
-    launch_axpy(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), S.d_runs, S.d_druns, R, stream);
+    launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, stream);
     HIPCHK(hipGetLastError());
     if (phase_ms) {
         HIPCHK(hipEventRecord(ev[3], (hipStream_t)stream));
@@ -90,8 +108,6 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
     std::vector<Desc> descs(count);
     std::vector<DotTask> dot;
     std::vector<LeafTask> leaf;
-    std::vector<Run> runs;
-    std::vector<DotRun> druns;
     int64_t max_np = 0;
     for (int t = 0; t < count; ++t) {
         hh_handle* h = const_cast<hh_handle*>(hs[t]);
@@ -102,23 +118,16 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
         for (int u = 0; u < t; ++u)
             if (hs[u] == h) fail(HH_EINVAL, "a handle appears twice in the batch (shared workspace)");
         ensure_workspace(h, nrhs);
-        descs[t] = Desc{h->xt, h->tb, h->d_pmap, x[t], y[t], h->np, io, 0};
+        descs[t] = make_desc(h, h->fwd, x[t], y[t]);
         max_np = std::max(max_np, h->np);
         for (DotTask k : h->fwd.dot) {
             k.hid = t;
             dot.push_back(k);
         }
-        const int32_t r0 = (int32_t)runs.size(), d0 = (int32_t)druns.size();
         for (LeafTask k : h->fwd.leaf) {
             k.hid = t;
-            k.run_begin += r0;
-            k.run_end += r0;
-            k.drun_begin += d0;
-            k.drun_end += d0;
             leaf.push_back(k);
         }
-        runs.insert(runs.end(), h->fwd.runs.begin(), h->fwd.runs.end());
-        druns.insert(druns.end(), h->fwd.druns.begin(), h->fwd.druns.end());
     }
     if (count > 65535) fail(HH_EINVAL, "at most 65535 handles per batch");
     // staging buffers for this call (freed after the stream drains)
@@ -131,12 +140,10 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
     Desc* dd = static_cast<Desc*>(up(descs.data(), descs.size() * sizeof(Desc)));
     DotTask* dt = static_cast<DotTask*>(up(dot.data(), dot.size() * sizeof(DotTask)));
     LeafTask* dl = static_cast<LeafTask*>(up(leaf.data(), leaf.size() * sizeof(LeafTask)));
-    Run* dr = static_cast<Run*>(up(runs.data(), runs.size() * sizeof(Run)));
-    DotRun* ddr = static_cast<DotRun*>(up(druns.data(), druns.size() * sizeof(DotRun)));
     const int R = (int)nrhs;
     launch_gather(descs[0], dd, count, max_np, R, stream);
     launch_dot(descs[0], dd, dt, (int64_t)dot.size(), R, stream);
-    launch_axpy(descs[0], dd, dl, (int64_t)leaf.size(), dr, ddr, R, stream);
+    launch_accumulate(descs[0], dd, dl, (int64_t)leaf.size(), R, stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
 }

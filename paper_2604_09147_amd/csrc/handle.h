@@ -22,12 +22,16 @@ struct DevMem {
 struct TaskSet {                      // one direction of the product
     std::vector<DotTask> dot;
     std::vector<LeafTask> leaf;
-    std::vector<Run> runs;
-    std::vector<DotRun> druns;
+    std::vector<Run> runs;            // grouped by cluster, clusters in (level, box) order
+    std::vector<int32_t> cl_run;      // sum_l 2^(d l) + 1 cluster boundaries
+    std::vector<DotRun> druns;        // grouped by leaf box
+    std::vector<int32_t> cl_drun;     // 2^(d L) + 1 leaf boundaries (empty: no druns)
     DotTask* d_dot = nullptr;
     LeafTask* d_leaf = nullptr;
     Run* d_runs = nullptr;
+    int32_t* d_cl_run = nullptr;
     DotRun* d_druns = nullptr;
+    int32_t* d_cl_drun = nullptr;
 };
 
 }  // namespace hh

@@ -45,16 +45,25 @@ void box_coords(int64_t box, int level, int d, int64_t* c);
 // that a wave lane owning 4 consecutive rows always reads aligned vectors.
 constexpr int ROW_PAD = 4;
 
-// Per-handle device pointers the product kernels need (passed by value, or as
-// an array indexed by DotTask::hid / LeafTask::hid in a batched launch).
+struct Run;
+struct DotRun;
+
+// Per-handle device pointers the product kernels need for one direction of the
+// product (passed by value, or as an array indexed by DotTask::hid /
+// LeafTask::hid in a batched launch).
 struct Desc {
     double* xt;              // gathered x, padded tree order, NP x R (row-major)
     double* tb;              // column coefficients, C x R (row-major)
     const int64_t* pmap;     // padded slot -> caller index (-1 = pad), NP entries
     const void* x;           // caller x (N x R)
     void* y;                 // caller y (N x R)
+    const Run* runs;         // runs of every cluster, clusters in (level, box) order
+    const int32_t* cl_run;   // runs of cluster c: [cl_run[c], cl_run[c + 1])
+    const DotRun* druns;     // transposed dense blocks by leaf (NULL: none)
+    const int32_t* cl_drun;  // druns of leaf box b: [cl_drun[b], cl_drun[b + 1])
     int64_t np;              // padded length
     int32_t io;              // HH_IO_F64 / HH_IO_F32
+    int32_t d, L;            // dimension and depth of the tree
     int32_t pad_;
 };
 
@@ -70,17 +79,19 @@ struct DotTask {
     int32_t hid;             // handle index in a batched launch
 };
 
-// A run of columns applied to one leaf: y_leaf += sum_c col_c coef_c scale,
+// The columns of one stored block restricted to the rows of a cluster (the
+// block's row cluster; for the transpose, its column cluster). Applied to a
+// leaf inside the cluster: y_leaf += 2^exp sum_c col_c[leaf rows] coef_c with
 // coef_c = tb[toff + c] (low-rank block) or xt[toff + c] (dense block).
 struct Run {
-    const void* base;        // element (leaf row 0, column 0)
-    int64_t stride;          // elements between consecutive columns
-    int64_t toff;
-    double scale;            // 2^(eU + eV), exact
+    const void* base;        // element (cluster row 0, column 0)
+    int64_t pc;              // padded offset of the cluster's first row
+    int32_t stride;          // elements between consecutive columns
+    int32_t toff;
     int32_t ncols;
-    int32_t fmt;             // HH_FMT_*; dense blocks are HH_FMT_FP64
-    int32_t from_x;
-    int32_t pad_;
+    int16_t exp;             // eU + eV
+    int8_t fmt;              // HH_FMT_*; dense blocks are HH_FMT_FP64
+    int8_t from_x;
 };
 
 // Transposed dense block applied to leaf mu: y_mu[j] += dot(D[:, j], xt_lambda).
@@ -91,12 +102,13 @@ struct DotRun {
     int32_t ncols;           // real points of mu
 };
 
+// One nonempty leaf box (one wave of the accumulation kernel).
 struct LeafTask {
     int64_t poff;            // padded offset of the leaf
     int32_t P;               // padded rows of the leaf
-    int32_t run_begin, run_end;
-    int32_t drun_begin, drun_end;
-    int32_t hid;
+    int32_t leaf;            // Morton index of the leaf box at level L
+    int32_t hid;             // handle index in a batched launch
+    int32_t pad_;
 };
 
 // Host record of one block after the build.
@@ -117,8 +129,8 @@ struct BlockRec {
 void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int R, void* stream);
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
                 int R, void* stream);
-void launch_axpy(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
-                 const Run* runs, const DotRun* druns, int R, void* stream);
+void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
+                       int R, void* stream);
 
 }  // namespace hh
 

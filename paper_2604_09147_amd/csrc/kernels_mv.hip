@@ -1,65 +1,116 @@
 // Product kernels of Alg. 4 on gfx950: b = sum_b U_b (V_b^T x_J) + sum D x.
 //
-// Phase 1 (gather):  xt = x in padded tree order (fp64).
-// Phase 2 (dot):     one coefficient per stored column, tb[c] = V_c . xt_J
-//                    (for the transpose, U_c . xt_I). One workgroup per task of
-//                    columns; a wave owns a column, each lane 4 consecutive rows.
-// Phase 3 (axpy):    one workgroup per leaf owns that leaf's output rows and
-//                    accumulates every column segment covering them
-//                    (U_c[leaf rows] tb[c] scale_b), the dense blocks, and, for
-//                    the transpose, the in-kernel transposed dense blocks; then
-//                    writes y in caller order. No atomics: results are bitwise
-//                    reproducible.
+// Phase 1 (gather):     xt = x in padded tree order (fp64).
+// Phase 2 (dot):        one coefficient per stored column, tb[c] = V_c . xt_J (for
+//                       the transpose, U_c . xt_I). One workgroup per task of
+//                       columns of one block; every wave keeps eight independent
+//                       4-row vector loads in flight (several columns of a short
+//                       column length, or several 256-row pieces of a long one).
+// Phase 3 (accumulate): one wave per leaf box owns that leaf's output rows. The
+//                       cluster containing the leaf at each level lists its runs
+//                       (the columns of one stored block, restricted to the
+//                       cluster's rows); the wave applies each run to its rows with
+//                       the coefficients tb[c] 2^e (low-rank) or xt (dense), then,
+//                       for the transpose, the transposed dense blocks, and writes
+//                       y in caller order. Run metadata and coefficients are
+//                       wave-uniform (scalar loads); only factor data moves through
+//                       the vector memory path. No atomics and a fixed order:
+//                       results are bitwise reproducible.
 // Factors stored in fp32 / fp64 and dense blocks use fp64 arithmetic; fp16 and
-// bf16 columns multiply and accumulate their lane partials in fp32.
+// bf16 inner products multiply and accumulate their lane partials in fp32.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "hh_internal.h"
 
 namespace hh {
 
+// Native vector types (HIP's double2 / float4 wrappers copy through a generic
+// pointer and would turn every load below back into a flat access).
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+// Loads through the global address space (vector memory path) and through the
+// constant address space (scalar loads when the address is wave-uniform).
+// Pointers read out of task records are generic; without these casts every
+// access would be a flat access, which also holds the LDS / scalar counter.
+template <class T>
+__device__ inline T ldg(const void* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline T ldc(const void* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+// A task record read as 64-bit words through the constant address space, so
+// that a wave-uniform record lands in scalar registers (an aggregate copy
+// would go through a generic pointer).
+template <class T>
+__device__ inline T ldrec(const T* p) {
+    static_assert(sizeof(T) % 8 == 0, "records are whole 64-bit words");
+    uint64_t w[sizeof(T) / 8];
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 8; ++i) w[i] = ldc<uint64_t>(reinterpret_cast<const uint64_t*>(p) + i);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+template <class T>
+__device__ inline void stg(void* p, T v) {
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// Four consecutive stored elements, still in their storage format.
+template <int FMT> struct Raw4;
+template <> struct Raw4<HH_FMT_FP64> { dbl2_t a, b; };
+template <> struct Raw4<HH_FMT_FP32> { flt4_t a; };
+template <> struct Raw4<HH_FMT_FP16> { half4_t a; };
+template <> struct Raw4<HH_FMT_BF16> { u32x2_t a; };
+
+template <int FMT>
+__device__ inline const void* elem_ptr(const void* base, int64_t i) {
+    if constexpr (FMT == HH_FMT_FP64) return static_cast<const double*>(base) + i;
+    else if constexpr (FMT == HH_FMT_FP32) return static_cast<const float*>(base) + i;
+    else return static_cast<const uint16_t*>(base) + i;
+}
+
+// Elements i .. i+3 (i a multiple of 4, so the access is aligned).
+template <int FMT>
+__device__ inline Raw4<FMT> load4(const void* base, int64_t i) {
+    Raw4<FMT> r;
+    const void* p = elem_ptr<FMT>(base, i);
+    if constexpr (FMT == HH_FMT_FP64) {
+        r.a = ldg<dbl2_t>(p);
+        r.b = ldg<dbl2_t>(static_cast<const dbl2_t*>(p) + 1);
+    } else if constexpr (FMT == HH_FMT_FP32) {
+        r.a = ldg<flt4_t>(p);
+    } else if constexpr (FMT == HH_FMT_FP16) {
+        r.a = ldg<half4_t>(p);
+    } else {
+        r.a = ldg<u32x2_t>(p);
+    }
+    return r;
+}
 
 __device__ inline float bf16lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ inline float bf16hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
-// Four consecutive elements starting at element index i (i multiple of 4).
-template <int FMT>
-__device__ inline void ld4(const void* base, int64_t i, double v[4]) {
+// Exact widening to T (float for 16-bit formats, double otherwise).
+template <int FMT, typename T>
+__device__ inline void widen4(const Raw4<FMT>& r, T v[4]) {
     if constexpr (FMT == HH_FMT_FP64) {
-        const double2* p = reinterpret_cast<const double2*>(static_cast<const double*>(base) + i);
-        double2 a = p[0], b = p[1];
-        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+        v[0] = r.a.x; v[1] = r.a.y; v[2] = r.b.x; v[3] = r.b.y;
     } else if constexpr (FMT == HH_FMT_FP32) {
-        float4 f = *reinterpret_cast<const float4*>(static_cast<const float*>(base) + i);
-        v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+        v[0] = r.a.x; v[1] = r.a.y; v[2] = r.a.z; v[3] = r.a.w;
     } else if constexpr (FMT == HH_FMT_FP16) {
-        half4_t h = *reinterpret_cast<const half4_t*>(static_cast<const _Float16*>(base) + i);
-        v[0] = (float)h.x; v[1] = (float)h.y; v[2] = (float)h.z; v[3] = (float)h.w;
+        v[0] = (float)r.a.x; v[1] = (float)r.a.y; v[2] = (float)r.a.z; v[3] = (float)r.a.w;
     } else {
-        uint2 u = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(base) + i);
-        v[0] = bf16lo(u.x); v[1] = bf16hi(u.x); v[2] = bf16lo(u.y); v[3] = bf16hi(u.y);
+        v[0] = bf16lo(r.a.x); v[1] = bf16hi(r.a.x); v[2] = bf16lo(r.a.y); v[3] = bf16hi(r.a.y);
     }
-}
-
-template <int FMT>
-__device__ inline void ld4f(const void* base, int64_t i, float v[4]) {
-    if constexpr (FMT == HH_FMT_FP16) {
-        half4_t h = *reinterpret_cast<const half4_t*>(static_cast<const _Float16*>(base) + i);
-        v[0] = (float)h.x; v[1] = (float)h.y; v[2] = (float)h.z; v[3] = (float)h.w;
-    } else {
-        uint2 u = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(base) + i);
-        v[0] = bf16lo(u.x); v[1] = bf16hi(u.x); v[2] = bf16lo(u.y); v[3] = bf16hi(u.y);
-    }
-}
-
-template <int FMT>
-__device__ inline const void* col_ptr(const void* base, int64_t elems) {
-    if constexpr (FMT == HH_FMT_FP64) return static_cast<const double*>(base) + elems;
-    else if constexpr (FMT == HH_FMT_FP32) return static_cast<const float*>(base) + elems;
-    else return static_cast<const uint16_t*>(base) + elems;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -68,290 +119,331 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ------------------------------------------------------------------ gather
 __global__ void gather_kernel(Desc d, const Desc* descs, int R) {
-    const Desc D = descs ? descs[blockIdx.y] : d;
+    const Desc D = descs ? ldrec<Desc>(descs + blockIdx.y) : d;
     const int64_t total = D.np * R;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         int64_t p = idx / R, r = idx - p * R;
-        int64_t u = D.pmap[p];
+        const int64_t u = ldg<int64_t>(D.pmap + p);
         double v = 0.0;
         if (u >= 0) {
-            if (D.io == HH_IO_F64) v = static_cast<const double*>(D.x)[u * R + r];
-            else v = (double)static_cast<const float*>(D.x)[u * R + r];
+            if (D.io == HH_IO_F64) v = ldg<double>(static_cast<const double*>(D.x) + u * R + r);
+            else v = (double)ldg<float>(static_cast<const float*>(D.x) + u * R + r);
         }
-        D.xt[idx] = v;
+        stg<double>(D.xt + idx, v);
     }
 }
 
 // --------------------------------------------------------------------- dot
 constexpr int XLDS = 4096;   // rows of xt staged in LDS for single-vector tasks
 
-template <int FMT>
-__device__ void dot_task_r1(const DotTask& t, const double* x, const double* xs, bool lds,
-                            double* tb, int wave, int lane) {
+// One iteration of a wave covers UC columns x UR pieces of 256 rows (UC UR =
+// NU, eight loads of 16 bytes per lane; four of 32 bytes for fp64).
+// Units past the last column or row re-read an in-bounds element and are
+// discarded (column clamped, weight zero), so every load is unconditional.
+template <int FMT, int UR>
+__device__ void dot_r1(const DotTask& t, const double* xg, const double* xs, bool lds,
+                       double* tb, int wave, int lane) {
+    constexpr int UC = (FMT == HH_FMT_FP64 ? 4 : 8) / UR;
+    using acc_t = typename std::conditional<(FMT >= HH_FMT_FP16), float, double>::type;
     const int P = t.P;
-    for (int c = wave; c < t.ncols; c += 4) {
-        const void* col = col_ptr<FMT>(t.col0, (int64_t)c * P);
-        double acc;
-        if constexpr (FMT >= HH_FMT_FP16) {
-            float a0 = 0.f, a1 = 0.f;
-            int r = 4 * lane;
-            for (; r + 256 < P; r += 512) {
-                float v[4], w[4];
-                ld4f<FMT>(col, r, v);
-                ld4f<FMT>(col, r + 256, w);
-                const double* xa = lds ? xs + r : x + r;
-                const double* xb = lds ? xs + r + 256 : x + r + 256;
+    for (int c0 = wave * UC; c0 < t.ncols; c0 += 4 * UC) {
+        acc_t a[UC];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    a0 = fmaf(v[q], (float)xa[q], a0);
-                    a1 = fmaf(w[q], (float)xb[q], a1);
+        for (int u = 0; u < UC; ++u) a[u] = 0;
+        for (int rb = 0; rb < P; rb += 256 * UR) {
+            Raw4<FMT> raw[UC][UR];
+#pragma unroll
+            for (int uc = 0; uc < UC; ++uc) {
+                const int c = c0 + uc < t.ncols ? c0 + uc : t.ncols - 1;
+#pragma unroll
+                for (int ur = 0; ur < UR; ++ur) {
+                    const int r = rb + 256 * ur + 4 * lane;
+                    raw[uc][ur] = load4<FMT>(t.col0, (int64_t)c * P + (r < P ? r : 0));
                 }
             }
-            if (r < P) {
-                float v[4];
-                ld4f<FMT>(col, r, v);
-                const double* xa = lds ? xs + r : x + r;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) a0 = fmaf(v[q], (float)xa[q], a0);
-            }
-            acc = (double)a0 + (double)a1;
-        } else {
-            double a0 = 0.0, a1 = 0.0;
-            int r = 4 * lane;
-            for (; r + 256 < P; r += 512) {
-                double v[4], w[4];
-                ld4<FMT>(col, r, v);
-                ld4<FMT>(col, r + 256, w);
-                const double* xa = lds ? xs + r : x + r;
-                const double* xb = lds ? xs + r + 256 : x + r + 256;
+            for (int ur = 0; ur < UR; ++ur) {
+                const int r = rb + 256 * ur + 4 * lane;
+                acc_t xv[4] = {0, 0, 0, 0};
+                if (r < P) {
+                    if (lds) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    a0 = fma(v[q], xa[q], a0);
-                    a1 = fma(w[q], xb[q], a1);
+                        for (int q = 0; q < 4; ++q) xv[q] = (acc_t)xs[r + q];
+                    } else {
+                        const dbl2_t x0 = ldg<dbl2_t>(xg + r), x1 = ldg<dbl2_t>(xg + r + 2);
+                        xv[0] = (acc_t)x0.x; xv[1] = (acc_t)x0.y; xv[2] = (acc_t)x1.x; xv[3] = (acc_t)x1.y;
+                    }
+                }
+#pragma unroll
+                for (int uc = 0; uc < UC; ++uc) {
+                    acc_t v[4];
+                    widen4<FMT, acc_t>(raw[uc][ur], v);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) a[uc] = fma(v[q], xv[q], a[uc]);
                 }
             }
-            if (r < P) {
-                double v[4];
-                ld4<FMT>(col, r, v);
-                const double* xa = lds ? xs + r : x + r;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a0 = fma(v[q], xa[q], a0);
-            }
-            acc = a0 + a1;
         }
-        acc = wave_sum(acc);
-        if (lane == 0) tb[t.toff + c] = acc;
+#pragma unroll
+        for (int uc = 0; uc < UC; ++uc) {
+            const double s = wave_sum((double)a[uc]);
+            if (lane == 0 && c0 + uc < t.ncols) stg<double>(tb + t.toff + c0 + uc, s);
+        }
     }
 }
 
-// Several right-hand sides, RC at a time (columns re-read per chunk).
+template <int FMT>
+__device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs, bool lds,
+                           double* tb, int wave, int lane) {
+    const int nb = (t.P + 255) / 256;
+    if (nb <= 1) dot_r1<FMT, 1>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 2) dot_r1<FMT, 2>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 4 || FMT == HH_FMT_FP64) dot_r1<FMT, 4>(t, xg, xs, lds, tb, wave, lane);
+    else dot_r1<FMT, (FMT == HH_FMT_FP64 ? 4 : 8)>(t, xg, xs, lds, tb, wave, lane);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void dot1_kernel(Desc d, const Desc* descs,
+                                                   const DotTask* tasks) {
+    __shared__ double xs[XLDS];
+    const DotTask t = ldrec<DotTask>(tasks + blockIdx.x);
+    const Desc D = descs ? ldrec<Desc>(descs + t.hid) : d;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const double* x = D.xt + t.xoff;
+    const bool lds = t.P <= XLDS;
+    if (lds) {
+        for (int i = threadIdx.x; i < t.P; i += 256) xs[i] = ldg<double>(x + i);
+        __syncthreads();
+    }
+    switch (t.fmt) {
+        case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64>(t, x, xs, lds, D.tb, wave, lane); break;
+        case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32>(t, x, xs, lds, D.tb, wave, lane); break;
+        case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16>(t, x, xs, lds, D.tb, wave, lane); break;
+        default: dot_r1_any<HH_FMT_BF16>(t, x, xs, lds, D.tb, wave, lane); break;
+    }
+}
+
+// Several right-hand sides, RC at a time (columns re-read per chunk of RC).
 template <int FMT, int RC>
-__device__ void dot_task_rn(const DotTask& t, const double* xt, double* tb, int R, int wave,
-                            int lane) {
+__device__ void dot_rn(const DotTask& t, const double* xt, double* tb, int R, int wave,
+                       int lane) {
+    using acc_t = typename std::conditional<(FMT >= HH_FMT_FP16), float, double>::type;
     const int P = t.P;
     for (int r0 = 0; r0 < R; r0 += RC) {
         const int nr = R - r0 < RC ? R - r0 : RC;
         for (int c = wave; c < t.ncols; c += 4) {
-            const void* col = col_ptr<FMT>(t.col0, (int64_t)c * P);
-            double acc[RC];
+            acc_t a[RC];
 #pragma unroll
-            for (int k = 0; k < RC; ++k) acc[k] = 0.0;
-            if constexpr (FMT >= HH_FMT_FP16) {
-                float fa[RC];
+            for (int k = 0; k < RC; ++k) a[k] = 0;
+            for (int r = 4 * lane; r < P; r += 256) {
+                acc_t v[4];
+                widen4<FMT, acc_t>(load4<FMT>(t.col0, (int64_t)c * P + r), v);
 #pragma unroll
-                for (int k = 0; k < RC; ++k) fa[k] = 0.f;
-                for (int r = 4 * lane; r < P; r += 256) {
-                    float v[4];
-                    ld4f<FMT>(col, r, v);
+                for (int q = 0; q < 4; ++q) {
+                    const double* xr = xt + (t.xoff + r + q) * R + r0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double* xr = xt + (t.xoff + r + q) * R + r0;
-#pragma unroll
-                        for (int k = 0; k < RC; ++k)
-                            if (k < nr) fa[k] = fmaf(v[q], (float)xr[k], fa[k]);
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < RC; ++k) acc[k] = fa[k];
-            } else {
-                for (int r = 4 * lane; r < P; r += 256) {
-                    double v[4];
-                    ld4<FMT>(col, r, v);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double* xr = xt + (t.xoff + r + q) * R + r0;
-#pragma unroll
-                        for (int k = 0; k < RC; ++k)
-                            if (k < nr) acc[k] = fma(v[q], xr[k], acc[k]);
-                    }
+                    for (int k = 0; k < RC; ++k)
+                        if (k < nr) a[k] = fma(v[q], (acc_t)ldg<double>(xr + k), a[k]);
                 }
             }
 #pragma unroll
             for (int k = 0; k < RC; ++k) {
-                double s = wave_sum(acc[k]);
-                if (lane == 0 && k < nr) tb[(t.toff + c) * R + r0 + k] = s;
+                const double s = wave_sum((double)a[k]);
+                if (lane == 0 && k < nr) stg<double>(tb + (t.toff + c) * R + r0 + k, s);
             }
         }
     }
 }
 
-__global__ __launch_bounds__(256) void dot_kernel(Desc d, const Desc* descs,
-                                                  const DotTask* tasks, int R) {
-    __shared__ double xs[XLDS];
-    const DotTask t = tasks[blockIdx.x];
-    const Desc D = descs ? descs[t.hid] : d;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (R == 1) {
-        const double* x = D.xt + t.xoff;
-        const bool lds = t.P <= XLDS;
-        if (lds) {
-            for (int i = tid; i < t.P; i += 256) xs[i] = x[i];
-            __syncthreads();
-        }
-        switch (t.fmt) {
-            case HH_FMT_FP64: dot_task_r1<HH_FMT_FP64>(t, x, xs, lds, D.tb, wave, lane); break;
-            case HH_FMT_FP32: dot_task_r1<HH_FMT_FP32>(t, x, xs, lds, D.tb, wave, lane); break;
-            case HH_FMT_FP16: dot_task_r1<HH_FMT_FP16>(t, x, xs, lds, D.tb, wave, lane); break;
-            default: dot_task_r1<HH_FMT_BF16>(t, x, xs, lds, D.tb, wave, lane); break;
-        }
-    } else {
-        switch (t.fmt) {
-            case HH_FMT_FP64: dot_task_rn<HH_FMT_FP64, 8>(t, D.xt, D.tb, R, wave, lane); break;
-            case HH_FMT_FP32: dot_task_rn<HH_FMT_FP32, 8>(t, D.xt, D.tb, R, wave, lane); break;
-            case HH_FMT_FP16: dot_task_rn<HH_FMT_FP16, 8>(t, D.xt, D.tb, R, wave, lane); break;
-            default: dot_task_rn<HH_FMT_BF16, 8>(t, D.xt, D.tb, R, wave, lane); break;
-        }
+__global__ __launch_bounds__(256) void dotn_kernel(Desc d, const Desc* descs,
+                                                   const DotTask* tasks, int R) {
+    const DotTask t = ldrec<DotTask>(tasks + blockIdx.x);
+    const Desc D = descs ? ldrec<Desc>(descs + t.hid) : d;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    switch (t.fmt) {
+        case HH_FMT_FP64: dot_rn<HH_FMT_FP64, 8>(t, D.xt, D.tb, R, wave, lane); break;
+        case HH_FMT_FP32: dot_rn<HH_FMT_FP32, 8>(t, D.xt, D.tb, R, wave, lane); break;
+        case HH_FMT_FP16: dot_rn<HH_FMT_FP16, 8>(t, D.xt, D.tb, R, wave, lane); break;
+        default: dot_rn<HH_FMT_BF16, 8>(t, D.xt, D.tb, R, wave, lane); break;
     }
 }
 
-// -------------------------------------------------------------------- axpy
-template <int FMT, int RC>
-__device__ inline void axpy_run(const Run& rn, const double* coef, int R, int r0, int nr,
-                                int gg, int TG, int64_t row, bool active, double acc[4][RC]) {
-    for (int c = gg; c < rn.ncols; c += TG) {
-        double cf[RC];
-        const double* cp = coef + (rn.toff + c) * R + r0;
+// -------------------------------------------------------------- accumulate
+// Apply one run to a lane's 4 rows: acc += 2^e sum_c col_c[rows] coef_c
+// (the power-of-two scale is exact, so applying it to the run's sum rounds as
+// applying it to every coefficient would). SPLIT: the wave is cut into G
+// groups of lps lanes (short leaves) and group g takes columns g, g + G, ...;
+// without SPLIT the column index and so the coefficient address are
+// wave-uniform.
+template <int FMT, int RC, bool SPLIT>
+__device__ inline void apply_run(const Run& rn, const void* base, const double* coef, int R,
+                                 int r0, int nr, int g, int G, double acc[4][RC]) {
+    constexpr int U = RC > 1 ? 2 : (SPLIT || FMT == HH_FMT_FP64) ? 8 : 16;
+    const int n = rn.ncols;
+    const int step = SPLIT ? G : 1;
+    double ra[4][RC];
 #pragma unroll
-        for (int k = 0; k < RC; ++k) cf[k] = k < nr ? cp[k] * rn.scale : 0.0;
-        if (active) {
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < RC; ++k) ra[q][k] = 0.0;
+    for (int c = SPLIT ? g : 0; c < n; c += U * step) {
+        Raw4<FMT> raw[U];
+        double cf[U][RC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int cu = c + u * step;
+            const int cc = cu < n ? cu : n - 1;
+            raw[u] = load4<FMT>(base, (int64_t)cc * rn.stride);
+            const double* cp = coef + ((int64_t)rn.toff + cc) * R + r0;
+#pragma unroll
+            for (int k = 0; k < RC; ++k) {
+                const double* ck = cp + (k < nr ? k : 0);
+                cf[u][k] = SPLIT ? ldg<double>(ck) : ldc<double>(ck);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = c + u * step < n;
             double v[4];
-            ld4<FMT>(rn.base, (int64_t)c * rn.stride + row, v);
+            widen4<FMT, double>(raw[u], v);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int k = 0; k < RC; ++k) {
+                const double w = (ok && k < nr) ? cf[u][k] : 0.0;
 #pragma unroll
-                for (int k = 0; k < RC; ++k) acc[q][k] = fma(v[q], cf[k], acc[q][k]);
+                for (int q = 0; q < 4; ++q) ra[q][k] = fma(v[q], w, ra[q][k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < RC; ++k) acc[q][k] += ldexp(ra[q][k], rn.exp);
+}
+
+template <int RC, bool SPLIT>
+__device__ inline void apply_cluster_runs(const Desc& D, const LeafTask& lt, int64_t row, int R,
+                                          int r0, int nr, int g, int G, double acc[4][RC]) {
+    int64_t first = 0;                       // index of level l's first cluster
+    for (int l = 0; l <= D.L; ++l) {
+        const int64_t ci = first + ((int64_t)lt.leaf >> (D.d * (D.L - l)));
+        first += (int64_t)1 << (D.d * l);
+        const int rb = ldc<int32_t>(D.cl_run + ci), re = ldc<int32_t>(D.cl_run + ci + 1);
+        for (int i = rb; i < re; ++i) {
+            const Run rn = ldrec<Run>(D.runs + i);
+            const double* coef = rn.from_x ? D.xt : D.tb;
+            const int64_t off = lt.poff - rn.pc + row;
+            switch (rn.fmt) {
+                case HH_FMT_FP64:
+                    apply_run<HH_FMT_FP64, RC, SPLIT>(rn, elem_ptr<HH_FMT_FP64>(rn.base, off), coef, R, r0, nr, g, G, acc);
+                    break;
+                case HH_FMT_FP32:
+                    apply_run<HH_FMT_FP32, RC, SPLIT>(rn, elem_ptr<HH_FMT_FP32>(rn.base, off), coef, R, r0, nr, g, G, acc);
+                    break;
+                case HH_FMT_FP16:
+                    apply_run<HH_FMT_FP16, RC, SPLIT>(rn, elem_ptr<HH_FMT_FP16>(rn.base, off), coef, R, r0, nr, g, G, acc);
+                    break;
+                default:
+                    apply_run<HH_FMT_BF16, RC, SPLIT>(rn, elem_ptr<HH_FMT_BF16>(rn.base, off), coef, R, r0, nr, g, G, acc);
+                    break;
+            }
         }
     }
 }
 
 template <int RC>
-__device__ void axpy_leaf(const Desc& D, const LeafTask& L, const Run* runs, const DotRun* druns,
-                          int R) {
-    __shared__ double part[256 * RC];
-    __shared__ double ydot[256 * RC];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int P = L.P;
+__device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R) {
+    const int P = lt.P;
     int lps = 1;
-    while (lps < 64 && 4 * lps < P) lps <<= 1;      // lanes per column segment
-    const int G = 64 / lps;                          // segments per wave
-    const int TG = 4 * G;                            // segments per workgroup
-    const int g = lane / lps, sl = lane % lps, gg = wave * G + g;
-    const int rows_per_stripe = 4 * lps;
-    const int nstripes = (P + rows_per_stripe - 1) / rows_per_stripe;
-
-    for (int r0 = 0; r0 < R; r0 += RC) {
-        const int nr = R - r0 < RC ? R - r0 : RC;
-        for (int s = 0; s < nstripes; ++s) {
-            const int64_t row = (int64_t)4 * (sl + (int64_t)lps * s);
-            const bool active = row < P;
+    while (lps < 64 && 4 * lps < P) lps <<= 1;  // lanes per column piece
+    const int G = 64 / lps, g = lane / lps, sl = lane % lps;
+    const int strip = 4 * lps;                   // rows per pass
+    for (int jlo = 0; jlo < P; jlo += strip) {
+        for (int r0 = 0; r0 < R; r0 += RC) {
+            const int nr = R - r0 < RC ? R - r0 : RC;
+            const int prow = jlo + 4 * sl;              // this lane's first row
+            const int64_t row = prow < P ? prow : 0;    // clamped: in bounds, never written
             double acc[4][RC];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < RC; ++k) acc[q][k] = 0.0;
-            for (int ri = L.run_begin; ri < L.run_end; ++ri) {
-                const Run rn = runs[ri];
-                const double* coef = rn.from_x ? D.xt : D.tb;
-                switch (rn.fmt) {
-                    case HH_FMT_FP64: axpy_run<HH_FMT_FP64, RC>(rn, coef, R, r0, nr, gg, TG, row, active, acc); break;
-                    case HH_FMT_FP32: axpy_run<HH_FMT_FP32, RC>(rn, coef, R, r0, nr, gg, TG, row, active, acc); break;
-                    case HH_FMT_FP16: axpy_run<HH_FMT_FP16, RC>(rn, coef, R, r0, nr, gg, TG, row, active, acc); break;
-                    default: axpy_run<HH_FMT_BF16, RC>(rn, coef, R, r0, nr, gg, TG, row, active, acc); break;
-                }
-            }
-            // combine the segments of one wave that cover the same rows
+            if (G == 1) apply_cluster_runs<RC, false>(D, lt, row, R, r0, nr, 0, 1, acc);
+            else apply_cluster_runs<RC, true>(D, lt, row, R, r0, nr, g, G, acc);
+            // groups covering the same rows, combined in a fixed order
             for (int off = lps; off < 64; off <<= 1)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int k = 0; k < RC; ++k) acc[q][k] += __shfl_xor(acc[q][k], off, 64);
-            // combine the waves in a fixed order
-            for (int w = 0; w < 4; ++w) {
-                if (wave == w && g == 0)
+            // transposed dense blocks: y_mu[j] += D[:, j] . xt_lambda
+            if (D.cl_drun) {
+                const int db = ldc<int32_t>(D.cl_drun + lt.leaf);
+                const int de = ldc<int32_t>(D.cl_drun + lt.leaf + 1);
+                for (int di = db; di < de; ++di) {
+                    const DotRun dr = ldrec<DotRun>(D.druns + di);
+                    const int jhi = dr.ncols < jlo + strip ? dr.ncols : jlo + strip;
+                    for (int j = jlo; j < jhi; ++j) {
+                        const double* col = dr.base + (int64_t)j * dr.P;
+                        double a[RC];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                        for (int k = 0; k < RC; ++k) a[k] = 0.0;
+                        for (int i = 4 * lane; i < dr.P; i += 256) {
+                            double v[4];
+                            widen4<HH_FMT_FP64, double>(load4<HH_FMT_FP64>(col, i), v);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const double* xr = D.xt + (dr.xoff + i + q) * R + r0;
+#pragma unroll
+                                for (int k = 0; k < RC; ++k)
+                                    if (k < nr) a[k] = fma(v[q], ldg<double>(xr + k), a[k]);
+                            }
+                        }
+                        const int jj = j - jlo;
 #pragma unroll
                         for (int k = 0; k < RC; ++k) {
-                            double& dst = part[(4 * sl + q) * RC + k];
-                            dst = (w == 0 ? 0.0 : dst) + acc[q][k];
+                            const double s = wave_sum(a[k]);
+                            if (lane == (jj >> 2))
+#pragma unroll
+                                for (int q = 0; q < 4; ++q)
+                                    if (q == (jj & 3)) acc[q][k] += s;
                         }
-                __syncthreads();
-            }
-            // transposed dense blocks: y_mu[j] += dot(D[:, j], xt_lambda)
-            for (int i = tid; i < rows_per_stripe * RC; i += 256) ydot[i] = 0.0;
-            __syncthreads();
-            const int jlo = s * rows_per_stripe;
-            for (int di = L.drun_begin; di < L.drun_end; ++di) {
-                const DotRun dr = druns[di];
-                const int jhi = dr.ncols < jlo + rows_per_stripe ? dr.ncols : jlo + rows_per_stripe;
-                for (int j = jlo + wave; j < jhi; j += 4) {
-                    const double* col = dr.base + (int64_t)j * dr.P;
-                    double a[RC];
-#pragma unroll
-                    for (int k = 0; k < RC; ++k) a[k] = 0.0;
-                    for (int i = lane; i < dr.P; i += 64) {
-                        const double v = col[i];
-                        const double* xr = D.xt + (dr.xoff + i) * R + r0;
-#pragma unroll
-                        for (int k = 0; k < RC; ++k)
-                            if (k < nr) a[k] = fma(v, xr[k], a[k]);
                     }
+                }
+            }
+            if (g == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (prow + q >= P) continue;
+                    const int64_t u = ldg<int64_t>(D.pmap + lt.poff + prow + q);
+                    if (u < 0) continue;
 #pragma unroll
                     for (int k = 0; k < RC; ++k) {
-                        double t = wave_sum(a[k]);
-                        if (lane == 0) ydot[(j - jlo) * RC + k] += t;
+                        if (k >= nr) continue;
+                        if (D.io == HH_IO_F64)
+                            stg<double>(static_cast<double*>(D.y) + u * R + r0 + k, acc[q][k]);
+                        else
+                            stg<float>(static_cast<float*>(D.y) + u * R + r0 + k, (float)acc[q][k]);
                     }
                 }
             }
-            __syncthreads();
-            // write this stripe of y in caller order
-            for (int i = tid; i < rows_per_stripe * RC; i += 256) {
-                const int rr = i / RC, k = i - rr * RC;
-                const int64_t prow = (int64_t)jlo + rr;
-                if (prow < P && k < nr) {
-                    const int64_t u = D.pmap[L.poff + prow];
-                    if (u >= 0) {
-                        const double v = part[rr * RC + k] + ydot[rr * RC + k];
-                        if (D.io == HH_IO_F64) static_cast<double*>(D.y)[u * R + r0 + k] = v;
-                        else static_cast<float*>(D.y)[u * R + r0 + k] = (float)v;
-                    }
-                }
-            }
-            __syncthreads();
         }
     }
 }
 
-__global__ __launch_bounds__(256) void axpy_kernel(Desc d, const Desc* descs,
-                                                   const LeafTask* leaves, const Run* runs,
-                                                   const DotRun* druns, int R) {
-    const LeafTask L = leaves[blockIdx.x];
-    const Desc D = descs ? descs[L.hid] : d;
-    if (R == 1) axpy_leaf<1>(D, L, runs, druns, R);
-    else axpy_leaf<4>(D, L, runs, druns, R);
+// Four leaves per workgroup, one per wave; the waves never synchronise.
+template <int RC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void accum_kernel(Desc d, const Desc* descs,
+                                                    const LeafTask* leaves, int64_t nleaves,
+                                                    int R) {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int64_t li = (int64_t)blockIdx.x * 4 + wave;
+    if (li >= nleaves) return;
+    const LeafTask lt = ldrec<LeafTask>(leaves + li);
+    const Desc D = descs ? ldrec<Desc>(descs + lt.hid) : d;
+    leaf_wave<RC>(D, lt, lane, R);
 }
 
 // ------------------------------------------------------------- launchers
@@ -367,15 +459,24 @@ void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks, int R,
                 void* stream) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(dot_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream, d,
-                       descs, tasks, R);
+    if (R == 1)
+        hipLaunchKernelGGL(dot1_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
+                           d, descs, tasks);
+    else
+        hipLaunchKernelGGL(dotn_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
+                           d, descs, tasks, R);
 }
 
-void launch_axpy(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
-                 const Run* runs, const DotRun* druns, int R, void* stream) {
+void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
+                       int R, void* stream) {
     if (nleaves <= 0) return;
-    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)nleaves), dim3(256), 0, (hipStream_t)stream, d,
-                       descs, leaves, runs, druns, R);
+    const unsigned grid = (unsigned)((nleaves + 3) / 4);
+    if (R == 1)
+        hipLaunchKernelGGL(accum_kernel<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, leaves, nleaves, R);
+    else
+        hipLaunchKernelGGL(accum_kernel<4>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, leaves, nleaves, R);
 }
 
 }  // namespace hh
