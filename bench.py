@@ -36,6 +36,27 @@ HBM_PEAK_GBS = 8000.0
 CPU_SAMPLE_N = 16384
 
 
+def measured_traffic(kernel: str, n: int, nrhs: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when there is none for this workload or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2604_09147_amd", "csrc", "kernels_mv.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_mv_sha256") != sha or rec.get("n") != n or rec.get("nrhs") != nrhs:
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
 def cpu_worker(out_path: str, budget_s: float) -> None:
     """Build the oracle on the sample instance and time its product."""
     import numpy as np
@@ -78,6 +99,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uniform", action="store_true", help="build the adaptive handle only")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-check", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -155,12 +178,22 @@ def main() -> int:
         res["speedup_vs_uniform_fp64"] = el_6 / el_a
         res["adaptive_vs_uniform_rel_diff"] = float(torch.linalg.norm(ya - y6) / torch.linalg.norm(y6))
 
+    if args.copy_check:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     names = ["gather", "column inner products", "leaf accumulation"]
+    kernels = ["gather_kernel", "dot1_kernel", "accum_kernel"]
     k = int(np.argmax(ph_a))
     achieved = sa["phase_bytes"][k] / (ph_a[k] / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None}
+                "traffic": measured_traffic(kernels[k], p.n, args.nrhs)}
 
     cpu = None
     if worker is not None:

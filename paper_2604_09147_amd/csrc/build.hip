@@ -47,6 +47,7 @@ constexpr int EXACT_SVD_MAX = 64;
 constexpr int SKETCH_START = 64;
 constexpr int OVERSAMPLE = 16;
 constexpr int64_t SUM_CHUNK = 65536;
+constexpr int64_t UNIT_BYTES = 1 << 20;   // factor bytes per single-vector work unit
 constexpr int64_t DOT_TASK_ELEMS = 65536;
 
 void* DevMem::alloc(size_t bytes, bool zero) {
@@ -959,11 +960,16 @@ static void build_tasks(hh_handle* h) {
                 dper[r.b.bj].push_back(dr);
             }
         }
-        S.cl_run.assign(ncl + 1, 0);
-        for (int64_t c = 0; c < ncl; ++c) {
-            S.runs.insert(S.runs.end(), per[c].begin(), per[c].end());
-            S.cl_run[c + 1] = (int32_t)S.runs.size();
-        }
+        // within a cluster, runs grouped by format (fp64, fp32, fp16, bf16),
+        // canonical block order inside a group
+        S.cl_run.assign(4 * ncl + 1, 0);
+        for (int64_t c = 0; c < ncl; ++c)
+            for (int f = 0; f < 4; ++f) {
+                S.cl_run[4 * c + f] = (int32_t)S.runs.size();
+                for (const Run& rn : per[c])
+                    if (rn.fmt == f) S.runs.push_back(rn);
+            }
+        S.cl_run[4 * ncl] = (int32_t)S.runs.size();
         if (dir == 1) {
             S.cl_drun.assign(nleaf + 1, 0);
             for (int64_t b = 0; b < nleaf; ++b) {
@@ -980,10 +986,57 @@ static void build_tasks(hh_handle* h) {
             lt.hid = 0;
             S.leaf.push_back(lt);
         }
+        // single-vector work units: each leaf's runs in (format, level) order,
+        // cut into slices of about UNIT_BYTES of factor data
+        int64_t po = 0;
+        for (const LeafTask& lt : S.leaf) {
+            FinishTask ft{};
+            ft.poff = lt.poff;
+            ft.po = po;
+            ft.P = lt.P;
+            ft.leaf = lt.leaf;
+            ft.hid = 0;
+            std::vector<const Run*> list;
+            for (int f = 0; f < 4; ++f)
+                for (int l = 0; l <= L; ++l) {
+                    const int64_t ci = first[l] + ((int64_t)lt.leaf >> (d * (L - l)));
+                    for (const Run& rn : per[ci])
+                        if (rn.fmt == f) list.push_back(&rn);
+                }
+            size_t a = 0;
+            while (a < list.size()) {
+                size_t e = a;
+                int64_t bytes = 0;
+                while (e < list.size() && bytes < UNIT_BYTES) {
+                    bytes += (int64_t)list[e]->ncols * lt.P * (int64_t)fmt_size(list[e]->fmt);
+                    ++e;
+                }
+                UnitTask ut{};
+                ut.poff = lt.poff;
+                ut.po = po;
+                ut.P = lt.P;
+                ut.rb = (int32_t)S.uruns.size();
+                for (int f = 0; f < 4; ++f) {
+                    for (size_t i = a; i < e; ++i)
+                        if (list[i]->fmt == f) S.uruns.push_back(*list[i]);
+                    ut.fe[f] = (int32_t)S.uruns.size();
+                }
+                ut.hid = 0;
+                S.unit.push_back(ut);
+                po += lt.P;
+                ft.nu++;
+                a = e;
+            }
+            S.fin.push_back(ft);
+        }
+        h->part_rows = std::max(h->part_rows, po);
     }
     for (TaskSet* S : {&F, &T}) {
         S->d_dot = upload(h->mem, S->dot);
         S->d_leaf = upload(h->mem, S->leaf);
+        S->d_unit = upload(h->mem, S->unit);
+        S->d_uruns = upload(h->mem, S->uruns);
+        S->d_fin = upload(h->mem, S->fin);
         S->d_runs = upload(h->mem, S->runs);
         S->d_cl_run = upload(h->mem, S->cl_run);
         S->d_druns = S->druns.empty() ? nullptr : upload(h->mem, S->druns);
@@ -1164,6 +1217,7 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
     h->ws_R = 1;
     h->xt = static_cast<double*>(h->mem.alloc((size_t)h->np * 8 + 256, true));
     h->tb = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->ncols, 1) * 8 + 256, true));
+    h->part = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->part_rows, 1) * 8 + 256, true));
     if (h->all_fp64) {
         // the fp64 store chunks are the arena: hand their ownership to the handle
         for (void* p : B.store.ptrs) h->mem.ptrs.push_back(p);
@@ -1239,6 +1293,7 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     h->ws_R = 1;
     h->xt = static_cast<double*>(h->mem.alloc((size_t)h->np * 8 + 256, true));
     h->tb = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->ncols, 1) * 8 + 256, true));
+    h->part = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->part_rows, 1) * 8 + 256, true));
     HIPCHK(hipDeviceSynchronize());
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(h.get(), secs);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -56,6 +57,8 @@ static Desc make_desc(const hh_handle* h, const TaskSet& S, const void* x, void*
     d.y = y;
     d.runs = S.d_runs;
     d.cl_run = S.d_cl_run;
+    d.uruns = S.d_uruns;
+    d.part = h->part;
     d.druns = S.d_druns;
     d.cl_drun = S.d_cl_drun;
     d.np = h->np;
@@ -86,7 +89,10 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
     launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[2], (hipStream_t)stream));
-    launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, stream);
+    if (R == 1)
+        launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(), stream);
+    else
+        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, stream);
     HIPCHK(hipGetLastError());
     if (phase_ms) {
         HIPCHK(hipEventRecord(ev[3], (hipStream_t)stream));
@@ -108,6 +114,8 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
     std::vector<Desc> descs(count);
     std::vector<DotTask> dot;
     std::vector<LeafTask> leaf;
+    std::vector<UnitTask> unit;
+    std::vector<FinishTask> fin;
     int64_t max_np = 0;
     for (int t = 0; t < count; ++t) {
         hh_handle* h = const_cast<hh_handle*>(hs[t]);
@@ -128,6 +136,14 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
             k.hid = t;
             leaf.push_back(k);
         }
+        for (UnitTask k : h->fwd.unit) {
+            k.hid = t;
+            unit.push_back(k);
+        }
+        for (FinishTask k : h->fwd.fin) {
+            k.hid = t;
+            fin.push_back(k);
+        }
     }
     if (count > 65535) fail(HH_EINVAL, "at most 65535 handles per batch");
     // staging buffers for this call (freed after the stream drains)
@@ -140,10 +156,15 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
     Desc* dd = static_cast<Desc*>(up(descs.data(), descs.size() * sizeof(Desc)));
     DotTask* dt = static_cast<DotTask*>(up(dot.data(), dot.size() * sizeof(DotTask)));
     LeafTask* dl = static_cast<LeafTask*>(up(leaf.data(), leaf.size() * sizeof(LeafTask)));
+    UnitTask* du = static_cast<UnitTask*>(up(unit.data(), unit.size() * sizeof(UnitTask)));
+    FinishTask* df = static_cast<FinishTask*>(up(fin.data(), fin.size() * sizeof(FinishTask)));
     const int R = (int)nrhs;
     launch_gather(descs[0], dd, count, max_np, R, stream);
     launch_dot(descs[0], dd, dt, (int64_t)dot.size(), R, stream);
-    launch_accumulate(descs[0], dd, dl, (int64_t)leaf.size(), R, stream);
+    if (R == 1)
+        launch_units(descs[0], dd, du, (int64_t)unit.size(), df, (int64_t)fin.size(), stream);
+    else
+        launch_accumulate(descs[0], dd, dl, (int64_t)leaf.size(), R, stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
 }

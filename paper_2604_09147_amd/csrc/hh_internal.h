@@ -58,7 +58,9 @@ struct Desc {
     const void* x;           // caller x (N x R)
     void* y;                 // caller y (N x R)
     const Run* runs;         // runs of every cluster, clusters in (level, box) order
-    const int32_t* cl_run;   // runs of cluster c: [cl_run[c], cl_run[c + 1])
+    const int32_t* cl_run;   // runs of cluster c in format f: [cl_run[4c + f], cl_run[4c + f + 1])
+    const Run* uruns;        // runs of the single-vector work units
+    double* part;            // partial sums of the work units
     const DotRun* druns;     // transposed dense blocks by leaf (NULL: none)
     const int32_t* cl_drun;  // druns of leaf box b: [cl_drun[b], cl_drun[b + 1])
     int64_t np;              // padded length
@@ -111,6 +113,31 @@ struct LeafTask {
     int32_t pad_;
 };
 
+// A slice of one leaf's runs (one wave of the single-vector accumulation).
+// Its runs in the unit run list are grouped by format: fp64 [rb, fe[0]),
+// fp32 [fe[0], fe[1]), fp16 [fe[1], fe[2]), bf16 [fe[2], fe[3]). The wave
+// writes its partial sum of the leaf's rows to part[po .. po + P).
+struct UnitTask {
+    int64_t poff;            // padded offset of the leaf
+    int64_t po;              // offset of the unit's partial rows
+    int32_t P;               // padded rows of the leaf
+    int32_t rb;
+    int32_t fe[4];
+    int32_t hid;             // handle index in a batched launch
+    int32_t pad_;
+};
+
+// One leaf of the finishing kernel: y rows = sum over its nu units of
+// part[po + k P + row], plus the transposed dense blocks of the leaf.
+struct FinishTask {
+    int64_t poff;
+    int64_t po;
+    int32_t P;
+    int32_t leaf;            // Morton index of the leaf box
+    int32_t nu;
+    int32_t hid;
+};
+
 // Host record of one block after the build.
 struct BlockRec {
     Blk b;
@@ -131,6 +158,8 @@ void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t 
                 int R, void* stream);
 void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
                        int R, void* stream);
+void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,
+                  const FinishTask* fin, int64_t nfin, void* stream);
 
 }  // namespace hh
 

@@ -96,6 +96,39 @@ __device__ inline Raw4<FMT> load4(const void* base, int64_t i) {
     return r;
 }
 
+// Buffer loads: a resource descriptor (base, byte size) in scalar registers
+// and a 32-bit byte offset per lane, so an address costs one vector register.
+// An offset at or past the descriptor's size reads zero instead of faulting.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;   // raw 32-bit data format (gfx9 family)
+
+__device__ inline rsrc_t make_rsrc(const void* base, int64_t bytes) {
+    const int nrec = bytes < 0x7fffffff ? (int)bytes : 0x7fffffff;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, RSRC_WORD3);
+}
+
+// Elements at byte offset off .. off + 4 elements of a buffer.
+template <int FMT>
+__device__ inline Raw4<FMT> bload4(rsrc_t rs, uint32_t off) {
+    Raw4<FMT> r;
+    if constexpr (FMT == HH_FMT_FP64) {
+        r.a = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        r.b = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+    } else if constexpr (FMT == HH_FMT_FP32) {
+        r.a = __builtin_bit_cast(flt4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    } else if constexpr (FMT == HH_FMT_FP16) {
+        r.a = __builtin_bit_cast(half4_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    } else {
+        r.a = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    }
+    return r;
+}
+
+template <int FMT>
+constexpr int elem_bytes() {
+    return FMT == HH_FMT_FP64 ? 8 : FMT == HH_FMT_FP32 ? 4 : 2;
+}
+
 __device__ inline float bf16lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ inline float bf16hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
@@ -279,8 +312,8 @@ __global__ __launch_bounds__(256) void dotn_kernel(Desc d, const Desc* descs,
 // without SPLIT the column index and so the coefficient address are
 // wave-uniform.
 template <int FMT, int RC, bool SPLIT>
-__device__ inline void apply_run(const Run& rn, const void* base, const double* coef, int R,
-                                 int r0, int nr, int g, int G, double acc[4][RC]) {
+__device__ inline void apply_run(const Run& rn, rsrc_t rs, uint32_t voff, const double* coef,
+                                 int R, int r0, int nr, int g, int G, double acc[4][RC]) {
     constexpr int U = RC > 1 ? 2 : (SPLIT || FMT == HH_FMT_FP64) ? 8 : 16;
     const int n = rn.ncols;
     const int step = SPLIT ? G : 1;
@@ -296,7 +329,7 @@ __device__ inline void apply_run(const Run& rn, const void* base, const double* 
         for (int u = 0; u < U; ++u) {
             const int cu = c + u * step;
             const int cc = cu < n ? cu : n - 1;
-            raw[u] = load4<FMT>(base, (int64_t)cc * rn.stride);
+            raw[u] = bload4<FMT>(rs, voff + (uint32_t)cc * (uint32_t)rn.stride * elem_bytes<FMT>());
             const double* cp = coef + ((int64_t)rn.toff + cc) * R + r0;
 #pragma unroll
             for (int k = 0; k < RC; ++k) {
@@ -323,38 +356,93 @@ __device__ inline void apply_run(const Run& rn, const void* base, const double* 
         for (int k = 0; k < RC; ++k) acc[q][k] += ldexp(ra[q][k], rn.exp);
 }
 
+// Index of the cluster of level l that contains leaf box `leaf`: clusters are
+// numbered level by level, level l starting at sum_{l' < l} 2^(d l').
+__device__ inline int64_t cluster_index(const Desc& D, int l, int64_t leaf) {
+    int64_t first = 0;
+    for (int i = 0; i < l; ++i) first += (int64_t)1 << (D.d * i);
+    return first + (leaf >> (D.d * (D.L - l)));
+}
+
+// The runs of one cluster stored in format F, applied to one leaf's rows.
+template <int F, int RC, bool SPLIT>
+__device__ inline void apply_runs_fmt(const Desc& D, const LeafTask& lt, int64_t ci, int64_t row,
+                                      int R, int r0, int nr, int g, int G, double acc[4][RC]) {
+    constexpr uint32_t es = elem_bytes<F>();
+    const int rb = ldc<int32_t>(D.cl_run + 4 * ci + F), re = ldc<int32_t>(D.cl_run + 4 * ci + F + 1);
+    for (int i = rb; i < re; ++i) {
+        const Run rn = ldrec<Run>(D.runs + i);
+        const double* coef = rn.from_x ? D.xt : D.tb;
+        // the run's columns from the leaf's first row on, as a buffer whose byte
+        // offsets are (column * stride + lane row) * element size
+        const int64_t off = lt.poff - rn.pc;
+        const rsrc_t rs = make_rsrc(static_cast<const char*>(rn.base) + off * es,
+                                    ((int64_t)rn.ncols * rn.stride - off) * es);
+        apply_run<F, RC, SPLIT>(rn, rs, (uint32_t)row * es, coef, R, r0, nr, g, G, acc);
+    }
+}
+
+// Runs of the clusters containing the leaf at levels lmin..L; each cluster
+// lists its runs grouped by storage format.
 template <int RC, bool SPLIT>
-__device__ inline void apply_cluster_runs(const Desc& D, const LeafTask& lt, int64_t row, int R,
-                                          int r0, int nr, int g, int G, double acc[4][RC]) {
-    int64_t first = 0;                       // index of level l's first cluster
-    for (int l = 0; l <= D.L; ++l) {
-        const int64_t ci = first + ((int64_t)lt.leaf >> (D.d * (D.L - l)));
-        first += (int64_t)1 << (D.d * l);
-        const int rb = ldc<int32_t>(D.cl_run + ci), re = ldc<int32_t>(D.cl_run + ci + 1);
-        for (int i = rb; i < re; ++i) {
-            const Run rn = ldrec<Run>(D.runs + i);
-            const double* coef = rn.from_x ? D.xt : D.tb;
-            const int64_t off = lt.poff - rn.pc + row;
-            switch (rn.fmt) {
-                case HH_FMT_FP64:
-                    apply_run<HH_FMT_FP64, RC, SPLIT>(rn, elem_ptr<HH_FMT_FP64>(rn.base, off), coef, R, r0, nr, g, G, acc);
-                    break;
-                case HH_FMT_FP32:
-                    apply_run<HH_FMT_FP32, RC, SPLIT>(rn, elem_ptr<HH_FMT_FP32>(rn.base, off), coef, R, r0, nr, g, G, acc);
-                    break;
-                case HH_FMT_FP16:
-                    apply_run<HH_FMT_FP16, RC, SPLIT>(rn, elem_ptr<HH_FMT_FP16>(rn.base, off), coef, R, r0, nr, g, G, acc);
-                    break;
-                default:
-                    apply_run<HH_FMT_BF16, RC, SPLIT>(rn, elem_ptr<HH_FMT_BF16>(rn.base, off), coef, R, r0, nr, g, G, acc);
-                    break;
+__device__ inline void apply_cluster_runs(const Desc& D, const LeafTask& lt, int lmin,
+                                          int64_t row, int R, int r0, int nr, int g, int G,
+                                          double acc[4][RC]) {
+    for (int l = lmin; l <= D.L; ++l) {
+        const int64_t ci = cluster_index(D, l, lt.leaf);
+        apply_runs_fmt<HH_FMT_FP64, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
+        apply_runs_fmt<HH_FMT_FP32, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
+        apply_runs_fmt<HH_FMT_FP16, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
+        apply_runs_fmt<HH_FMT_BF16, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
+    }
+}
+
+// Transposed dense blocks of leaf mu (column cluster mu at the leaf level):
+// y_mu[j] += D[:, j] . xt_lambda for the rows j of the strip [jlo, jlo + strip);
+// row j's sum goes to lane j / 4 (the lane that holds it after the combine).
+template <int RC>
+__device__ inline void add_transposed_dense(const Desc& D, int leaf, int jlo, int strip, int lane,
+                                            int R, int r0, int nr, double acc[4][RC]) {
+    const int db = ldc<int32_t>(D.cl_drun + leaf), de = ldc<int32_t>(D.cl_drun + leaf + 1);
+    for (int di = db; di < de; ++di) {
+        const DotRun dr = ldrec<DotRun>(D.druns + di);
+        const int jhi = dr.ncols < jlo + strip ? dr.ncols : jlo + strip;
+        for (int j = jlo; j < jhi; ++j) {
+            const double* col = dr.base + (int64_t)j * dr.P;
+            double a[RC];
+#pragma unroll
+            for (int k = 0; k < RC; ++k) a[k] = 0.0;
+            for (int i = 4 * lane; i < dr.P; i += 256) {
+                double v[4];
+                widen4<HH_FMT_FP64, double>(load4<HH_FMT_FP64>(col, i), v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double* xr = D.xt + (dr.xoff + i + q) * R + r0;
+#pragma unroll
+                    for (int k = 0; k < RC; ++k)
+                        if (k < nr) a[k] = fma(v[q], ldg<double>(xr + k), a[k]);
+                }
+            }
+            const int jj = j - jlo;
+#pragma unroll
+            for (int k = 0; k < RC; ++k) {
+                const double s = wave_sum(a[k]);
+                if (lane == (jj >> 2))
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q == (jj & 3)) acc[q][k] += s;
             }
         }
     }
 }
 
+// The output rows of one leaf: runs of its clusters at levels lmin..L (the
+// levels above lmin already summed into init, which only a single-vector
+// product of a leaf of at most 256 rows passes), transposed dense blocks, and
+// the write of y.
 template <int RC>
-__device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R) {
+__device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R, int lmin,
+                          double i0, double i1, double i2, double i3) {
     const int P = lt.P;
     int lps = 1;
     while (lps < 64 && 4 * lps < P) lps <<= 1;  // lanes per column piece
@@ -370,49 +458,18 @@ __device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R) {
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < RC; ++k) acc[q][k] = 0.0;
-            if (G == 1) apply_cluster_runs<RC, false>(D, lt, row, R, r0, nr, 0, 1, acc);
-            else apply_cluster_runs<RC, true>(D, lt, row, R, r0, nr, g, G, acc);
+            if (jlo == 0 && r0 == 0 && g == 0) {
+                acc[0][0] = i0; acc[1][0] = i1; acc[2][0] = i2; acc[3][0] = i3;
+            }
+            if (G == 1) apply_cluster_runs<RC, false>(D, lt, lmin, row, R, r0, nr, 0, 1, acc);
+            else apply_cluster_runs<RC, true>(D, lt, lmin, row, R, r0, nr, g, G, acc);
             // groups covering the same rows, combined in a fixed order
             for (int off = lps; off < 64; off <<= 1)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int k = 0; k < RC; ++k) acc[q][k] += __shfl_xor(acc[q][k], off, 64);
-            // transposed dense blocks: y_mu[j] += D[:, j] . xt_lambda
-            if (D.cl_drun) {
-                const int db = ldc<int32_t>(D.cl_drun + lt.leaf);
-                const int de = ldc<int32_t>(D.cl_drun + lt.leaf + 1);
-                for (int di = db; di < de; ++di) {
-                    const DotRun dr = ldrec<DotRun>(D.druns + di);
-                    const int jhi = dr.ncols < jlo + strip ? dr.ncols : jlo + strip;
-                    for (int j = jlo; j < jhi; ++j) {
-                        const double* col = dr.base + (int64_t)j * dr.P;
-                        double a[RC];
-#pragma unroll
-                        for (int k = 0; k < RC; ++k) a[k] = 0.0;
-                        for (int i = 4 * lane; i < dr.P; i += 256) {
-                            double v[4];
-                            widen4<HH_FMT_FP64, double>(load4<HH_FMT_FP64>(col, i), v);
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const double* xr = D.xt + (dr.xoff + i + q) * R + r0;
-#pragma unroll
-                                for (int k = 0; k < RC; ++k)
-                                    if (k < nr) a[k] = fma(v[q], ldg<double>(xr + k), a[k]);
-                            }
-                        }
-                        const int jj = j - jlo;
-#pragma unroll
-                        for (int k = 0; k < RC; ++k) {
-                            const double s = wave_sum(a[k]);
-                            if (lane == (jj >> 2))
-#pragma unroll
-                                for (int q = 0; q < 4; ++q)
-                                    if (q == (jj & 3)) acc[q][k] += s;
-                        }
-                    }
-                }
-            }
+            if (D.cl_drun) add_transposed_dense<RC>(D, lt.leaf, jlo, strip, lane, R, r0, nr, acc);
             if (g == 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -443,7 +500,96 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
     if (li >= nleaves) return;
     const LeafTask lt = ldrec<LeafTask>(leaves + li);
     const Desc D = descs ? ldrec<Desc>(descs + lt.hid) : d;
-    leaf_wave<RC>(D, lt, lane, R);
+    leaf_wave<RC>(D, lt, lane, R, 0, 0.0, 0.0, 0.0, 0.0);
+}
+
+// ---------------------------------------------- single-vector work units
+// A unit is a slice of one leaf's runs (a few hundred KB to about 1 MB of
+// factor data), so that the hardware dispatcher balances leaves of unequal
+// work. Each unit writes its partial sum of the leaf's rows; the finishing
+// kernel adds a leaf's partials in unit order.
+template <int F, bool SPLIT>
+__device__ inline void unit_runs_fmt(const Desc& D, const UnitTask& ut, int b, int e, int64_t row,
+                                     int g, int G, double acc[4][1]) {
+    constexpr uint32_t es = elem_bytes<F>();
+    for (int i = b; i < e; ++i) {
+        const Run rn = ldrec<Run>(D.uruns + i);
+        const double* coef = rn.from_x ? D.xt : D.tb;
+        const int64_t off = ut.poff - rn.pc;
+        const rsrc_t rs = make_rsrc(static_cast<const char*>(rn.base) + off * es,
+                                    ((int64_t)rn.ncols * rn.stride - off) * es);
+        apply_run<F, 1, SPLIT>(rn, rs, (uint32_t)row * es, coef, 1, 0, 1, g, G, acc);
+    }
+}
+
+template <bool SPLIT>
+__device__ inline void unit_runs(const Desc& D, const UnitTask& ut, int64_t row, int g, int G,
+                                 double acc[4][1]) {
+    unit_runs_fmt<HH_FMT_FP64, SPLIT>(D, ut, ut.rb, ut.fe[0], row, g, G, acc);
+    unit_runs_fmt<HH_FMT_FP32, SPLIT>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc);
+    unit_runs_fmt<HH_FMT_FP16, SPLIT>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc);
+    unit_runs_fmt<HH_FMT_BF16, SPLIT>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc);
+}
+
+// Four units per workgroup, one per wave; the waves never synchronise.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void unit_kernel(
+    Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int64_t ui = (int64_t)blockIdx.x * 4 + wave;
+    if (ui >= nunits) return;
+    const UnitTask ut = ldrec<UnitTask>(units + ui);
+    const Desc D = descs ? ldrec<Desc>(descs + ut.hid) : d;
+    const int P = ut.P;
+    int lps = 1;
+    while (lps < 64 && 4 * lps < P) lps <<= 1;
+    const int G = 64 / lps, g = lane / lps, sl = lane % lps;
+    const int strip = 4 * lps;
+    for (int jlo = 0; jlo < P; jlo += strip) {
+        const int prow = jlo + 4 * sl;
+        const int64_t row = prow < P ? prow : 0;     // clamped: in bounds, never written
+        double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
+        if (G == 1) unit_runs<false>(D, ut, row, 0, 1, acc);
+        else unit_runs<true>(D, ut, row, g, G, acc);
+        for (int off = lps; off < 64; off <<= 1)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][0] += __shfl_xor(acc[q][0], off, 64);
+        if (g == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (prow + q < P) stg<double>(D.part + ut.po + prow + q, acc[q][0]);
+    }
+}
+
+// y rows of one leaf: its units' partials in order, then (transpose) the
+// transposed dense blocks; written in caller order. Lane l owns rows 4l..4l+3
+// of each 256-row strip.
+__global__ __launch_bounds__(256) void finish_kernel(Desc d, const Desc* descs,
+                                                     const FinishTask* fin, int64_t nfin) {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int64_t fi = (int64_t)blockIdx.x * 4 + wave;
+    if (fi >= nfin) return;
+    const FinishTask ft = ldrec<FinishTask>(fin + fi);
+    const Desc D = descs ? ldrec<Desc>(descs + ft.hid) : d;
+    const int P = ft.P;
+    for (int jlo = 0; jlo < P; jlo += 256) {
+        const int prow = jlo + 4 * lane;
+        double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
+        if (prow < P)
+            for (int k = 0; k < ft.nu; ++k) {
+                const double* pp = D.part + ft.po + (int64_t)k * P + prow;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q][0] += ldg<double>(pp + q);
+            }
+        if (D.cl_drun) add_transposed_dense<1>(D, ft.leaf, jlo, 256, lane, 1, 0, 1, acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (prow + q >= P) continue;
+            const int64_t u = ldg<int64_t>(D.pmap + ft.poff + prow + q);
+            if (u < 0) continue;
+            if (D.io == HH_IO_F64) stg<double>(static_cast<double*>(D.y) + u, acc[q][0]);
+            else stg<float>(static_cast<float*>(D.y) + u, (float)acc[q][0]);
+        }
+    }
 }
 
 // ------------------------------------------------------------- launchers
@@ -471,12 +617,18 @@ void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves,
                        int R, void* stream) {
     if (nleaves <= 0) return;
     const unsigned grid = (unsigned)((nleaves + 3) / 4);
-    if (R == 1)
-        hipLaunchKernelGGL(accum_kernel<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
-                           descs, leaves, nleaves, R);
-    else
-        hipLaunchKernelGGL(accum_kernel<4>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
-                           descs, leaves, nleaves, R);
+    hipLaunchKernelGGL(accum_kernel<4>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
+                       leaves, nleaves, R);
+}
+
+void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,
+                  const FinishTask* fin, int64_t nfin, void* stream) {
+    if (nunits > 0)
+        hipLaunchKernelGGL(unit_kernel, dim3((unsigned)((nunits + 3) / 4)), dim3(256), 0,
+                           (hipStream_t)stream, d, descs, units, nunits);
+    if (nfin > 0)
+        hipLaunchKernelGGL(finish_kernel, dim3((unsigned)((nfin + 3) / 4)), dim3(256), 0,
+                           (hipStream_t)stream, d, descs, fin, nfin);
 }
 
 }  // namespace hh
