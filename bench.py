@@ -164,6 +164,7 @@ def main() -> int:
     sa = Ha.stats()
     res = {"adaptive": {"matvec_per_s": args.steps / el_a, "ms_per_step": 1000 * el_a / args.steps,
                         "phase_ms": [round(v, 4) for v in ph_a],
+                        "phase_bytes": [int(v) for v in sa["phase_bytes"]],
                         "bytes_per_matvec": sa["matvec_bytes"],
                         "hbm_gbs": sa["matvec_bytes"] / (el_a / args.steps) / 1e9,
                         "blocks_by_format": sa["blocks_by_format"]}}
@@ -173,6 +174,7 @@ def main() -> int:
         res["uniform_fp64"] = {"matvec_per_s": args.steps / el_6,
                                "ms_per_step": 1000 * el_6 / args.steps,
                                "phase_ms": [round(v, 4) for v in ph_6],
+                               "phase_bytes": [int(v) for v in s6["phase_bytes"]],
                                "bytes_per_matvec": s6["matvec_bytes"],
                                "hbm_gbs": s6["matvec_bytes"] / (el_6 / args.steps) / 1e9}
         res["speedup_vs_uniform_fp64"] = el_6 / el_a
