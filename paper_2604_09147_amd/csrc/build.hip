@@ -16,6 +16,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -784,7 +785,14 @@ struct Builder {
         }
         bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0;
         h->all_fp64 = all64;
-        if (all64 && in_place_ok) return;   // the fp64 store already is the arena
+        if (all64 && in_place_ok) {
+            // The fp64 store can serve as the arena as it is; it is re-laid in
+            // cluster order (longer runs in the product) only if a second copy
+            // fits in free device memory with 4 GiB to spare.
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            if ((double)fr < (double)need[0] * 8.0 + (double)(4ull << 30)) return;
+        }
         // exponents of the scaled formats
         std::vector<double> mx(2 * lr.size(), 0.0);
         {
@@ -807,7 +815,16 @@ struct Builder {
         char* arena[4] = {nullptr, nullptr, nullptr, nullptr};
         for (int f = 0; f < 4; ++f)
             if (need[f]) arena[f] = static_cast<char*>(h->mem.alloc((size_t)need[f] * fmt_size(f) + 256, false));
-        int64_t off[4] = {0, 0, 0, 0};
+        // Arena of a format: every U in (level, row box, column box) order, then
+        // every V in (level, column box, row box) order, so that the factors
+        // of one cluster and format follow each other (one strided matrix).
+        int64_t offU[4] = {0, 0, 0, 0}, offV[4] = {0, 0, 0, 0};
+        for (int64_t i : lr) offV[h->blocks[i].fmt] += (int64_t)h->blocks[i].rank * h->blocks[i].PI;
+        std::vector<int64_t> lr_t(lr);
+        std::stable_sort(lr_t.begin(), lr_t.end(), [&](int64_t x, int64_t y) {
+            const Blk &a = h->blocks[x].b, &b = h->blocks[y].b;
+            return std::make_tuple(a.level, a.bj, a.bi) < std::make_tuple(b.level, b.bj, b.bi);
+        });
         std::vector<PackItem> items;
         int64_t maxcount = 0;
         for (size_t a = 0; a < lr.size(); ++a) {
@@ -820,16 +837,27 @@ struct Builder {
             };
             r.eU = expo(mx[2 * a]);
             r.eV = expo(mx[2 * a + 1]);
-            const size_t es = fmt_size(r.fmt);
-            char* up = arena[r.fmt] + off[r.fmt] * es;
-            off[r.fmt] += (int64_t)r.rank * r.PI;
-            char* vp = arena[r.fmt] + off[r.fmt] * es;
-            off[r.fmt] += (int64_t)r.rank * r.PJ;
+        }
+        std::vector<const void*> newU(h->blocks.size(), nullptr), newV(h->blocks.size(), nullptr);
+        for (int64_t i : lr) {
+            BlockRec& r = h->blocks[i];
+            char* up = arena[r.fmt] + offU[r.fmt] * fmt_size(r.fmt);
+            offU[r.fmt] += (int64_t)r.rank * r.PI;
             items.push_back(PackItem{(const double*)r.u_ptr, up, (int64_t)r.rank * r.PI, r.fmt, r.eU});
+            maxcount = std::max(maxcount, (int64_t)r.rank * r.PI);
+            newU[i] = up;
+        }
+        for (int64_t i : lr_t) {
+            BlockRec& r = h->blocks[i];
+            char* vp = arena[r.fmt] + offV[r.fmt] * fmt_size(r.fmt);
+            offV[r.fmt] += (int64_t)r.rank * r.PJ;
             items.push_back(PackItem{(const double*)r.v_ptr, vp, (int64_t)r.rank * r.PJ, r.fmt, r.eV});
-            maxcount = std::max(maxcount, std::max((int64_t)r.rank * r.PI, (int64_t)r.rank * r.PJ));
-            r.u_ptr = up;
-            r.v_ptr = vp;
+            maxcount = std::max(maxcount, (int64_t)r.rank * r.PJ);
+            newV[i] = vp;
+        }
+        for (int64_t i : lr) {
+            h->blocks[i].u_ptr = newU[i];
+            h->blocks[i].v_ptr = newV[i];
         }
         for (size_t a = 0; a < items.size(); a += 32768) {
             size_t e = std::min(items.size(), a + 32768);
@@ -877,20 +905,50 @@ static void layout(hh_handle* h) {
     }
 }
 
+// Blocks grouped for one direction of the product: by (level, row box) for
+// H, by (level, column box) for H^T, each group in storage-format order
+// (fp64, fp32, fp16, bf16) and then by the other box index. Factor arenas and
+// coefficient indices follow these orders, so the blocks of one group and
+// format are one strided matrix with consecutive coefficients.
+static std::vector<int64_t> direction_order(const hh_handle* h, bool trans) {
+    std::vector<int64_t> idx;
+    for (size_t i = 0; i < h->blocks.size(); ++i) idx.push_back((int64_t)i);
+    auto key = [&](int64_t i) {
+        const BlockRec& r = h->blocks[i];
+        const int f = r.lowrank ? r.fmt : HH_FMT_FP64;
+        return trans ? std::make_tuple(r.b.level, r.b.bj, f, r.b.bi)
+                     : std::make_tuple(r.b.level, r.b.bi, f, r.b.bj);
+    };
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return key(x) < key(y); });
+    return idx;
+}
+
 static void build_tasks(hh_handle* h) {
     const Plan& P = h->plan;
     const int L = P.L, d = P.d;
-    int64_t col = 0;
-    for (auto& r : h->blocks)
+    const std::vector<int64_t> ord_f = direction_order(h, false), ord_t = direction_order(h, true);
+    int64_t col = 0, col_t = 0;
+    for (int64_t i : ord_f) {
+        BlockRec& r = h->blocks[i];
         if (r.lowrank && r.rank > 0) {
             r.col = col;
             col += r.rank;
         }
+    }
+    for (int64_t i : ord_t) {
+        BlockRec& r = h->blocks[i];
+        if (r.lowrank && r.rank > 0) {
+            r.col_t = col_t;
+            col_t += r.rank;
+        }
+    }
     h->ncols = col;
     TaskSet& F = h->fwd;
     TaskSet& T = h->bwd;
     if (h->np >= ((int64_t)1 << 31) || h->ncols >= ((int64_t)1 << 31))
         fail(HH_ENOTSUP, "padded length and stored columns must stay below 2^31");
+    // phase V tasks: the forward product dots V with x_J into tb[col], the
+    // transpose dots U with x_I into tb[col_t]; the factor scales go into tb
     for (const auto& r : h->blocks) {
         if (!(r.lowrank && r.rank > 0)) continue;
         const size_t es = fmt_size(r.fmt);
@@ -904,52 +962,49 @@ static void build_tasks(hh_handle* h) {
                 DotTask t{};
                 t.col0 = base + (size_t)(c0 * Pl) * es;
                 t.xoff = pass == 0 ? r.pJ : r.pI;
-                t.toff = r.col + c0;
+                t.toff = (pass == 0 ? r.col : r.col_t) + c0;
                 t.P = (int32_t)Pl;
                 t.ncols = (int32_t)std::min<int64_t>(cpt, r.rank - c0);
                 t.fmt = r.fmt;
                 t.hid = 0;
+                t.exp = r.eU + r.eV;
                 (pass == 0 ? F : T).dot.push_back(t);
             }
         }
     }
     // clusters in (level, box) order; cluster (l, b) has index
-    // sum_{l' < l} 2^(d l') + b. Blocks join the cluster of their row box
-    // (forward) or column box (transpose), in canonical block order.
+    // sum_{l' < l} 2^(d l') + b
     std::vector<int64_t> first(L + 2, 0);
     for (int l = 0; l <= L; ++l) first[l + 1] = first[l] + ((int64_t)1 << (d * l));
     const int64_t ncl = first[L + 1];
     const int64_t nleaf = (int64_t)1 << (d * L);
     for (int dir = 0; dir < 2; ++dir) {
         TaskSet& S = dir == 0 ? F : T;
+        const std::vector<int64_t>& ord = dir == 0 ? ord_f : ord_t;
         std::vector<std::vector<Run>> per(ncl);
         std::vector<std::vector<DotRun>> dper(dir == 1 ? nleaf : 0);
-        for (const auto& r : h->blocks) {
+        for (int64_t bi : ord) {
+            const BlockRec& r = h->blocks[bi];
             const int64_t box = dir == 0 ? r.b.bi : r.b.bj;
             const int64_t ci = first[r.b.level] + box;
+            Run rn{};
             if (r.lowrank) {
                 if (r.rank == 0) continue;
-                Run rn{};
                 rn.base = dir == 0 ? r.u_ptr : r.v_ptr;
                 rn.pc = dir == 0 ? r.pI : r.pJ;
                 rn.stride = (int32_t)(dir == 0 ? r.PI : r.PJ);
-                rn.toff = (int32_t)r.col;
+                rn.toff = (int32_t)(dir == 0 ? r.col : r.col_t);
                 rn.ncols = r.rank;
-                rn.exp = (int16_t)(r.eU + r.eV);
                 rn.fmt = (int8_t)r.fmt;
                 rn.from_x = 0;
-                per[ci].push_back(rn);
             } else if (dir == 0) {
-                Run rn{};
                 rn.base = r.d_ptr;
                 rn.pc = r.pI;
                 rn.stride = (int32_t)r.PI;
                 rn.toff = (int32_t)r.pJ;
                 rn.ncols = (int32_t)(r.b.je - r.b.jb);
-                rn.exp = 0;
                 rn.fmt = HH_FMT_FP64;
                 rn.from_x = 1;
-                per[ci].push_back(rn);
             } else {
                 if (r.b.level != L) fail(HH_EINTERNAL, "dense block above the leaf level");
                 DotRun dr{};
@@ -958,10 +1013,23 @@ static void build_tasks(hh_handle* h) {
                 dr.P = (int32_t)r.PI;
                 dr.ncols = (int32_t)(r.b.je - r.b.jb);
                 dper[r.b.bj].push_back(dr);
+                continue;
             }
+            // merge with the previous run when the columns continue it
+            std::vector<Run>& lst = per[ci];
+            if (!lst.empty() && !rn.from_x) {
+                Run& pr = lst.back();
+                const char* end = static_cast<const char*>(pr.base) +
+                                  (size_t)pr.ncols * pr.stride * fmt_size(pr.fmt);
+                if (!pr.from_x && pr.fmt == rn.fmt && pr.stride == rn.stride && pr.pc == rn.pc &&
+                    end == rn.base && pr.toff + pr.ncols == rn.toff) {
+                    pr.ncols += rn.ncols;
+                    continue;
+                }
+            }
+            lst.push_back(rn);
         }
-        // within a cluster, runs grouped by format (fp64, fp32, fp16, bf16),
-        // canonical block order inside a group
+        // within a cluster, runs grouped by format (fp64, fp32, fp16, bf16)
         S.cl_run.assign(4 * ncl + 1, 0);
         for (int64_t c = 0; c < ncl; ++c)
             for (int f = 0; f < 4; ++f) {
@@ -987,8 +1055,10 @@ static void build_tasks(hh_handle* h) {
             S.leaf.push_back(lt);
         }
         // single-vector work units: each leaf's runs in (format, level) order,
-        // cut into slices of about UNIT_BYTES of factor data
+        // cut into slices of about UNIT_BYTES of factor data (long runs are
+        // split by columns)
         int64_t po = 0;
+        std::vector<std::vector<UnitTask>> by_leaf;
         for (const LeafTask& lt : S.leaf) {
             FinishTask ft{};
             ft.poff = lt.poff;
@@ -996,19 +1066,31 @@ static void build_tasks(hh_handle* h) {
             ft.P = lt.P;
             ft.leaf = lt.leaf;
             ft.hid = 0;
-            std::vector<const Run*> list;
+            std::vector<Run> list;                   // pieces in processing order
             for (int f = 0; f < 4; ++f)
                 for (int l = 0; l <= L; ++l) {
                     const int64_t ci = first[l] + ((int64_t)lt.leaf >> (d * (L - l)));
-                    for (const Run& rn : per[ci])
-                        if (rn.fmt == f) list.push_back(&rn);
+                    for (const Run& rn : per[ci]) {
+                        if (rn.fmt != f) continue;
+                        const int64_t colb = std::max<int64_t>(1, UNIT_BYTES / ((int64_t)lt.P * fmt_size(f)));
+                        for (int32_t c0 = 0; c0 < rn.ncols; c0 += (int32_t)colb) {
+                            Run sub = rn;
+                            sub.base = static_cast<const char*>(rn.base) + (size_t)c0 * rn.stride * fmt_size(f);
+                            sub.toff = rn.toff + c0;
+                            sub.ncols = (int32_t)std::min<int64_t>(colb, rn.ncols - c0);
+                            list.push_back(sub);
+                        }
+                    }
                 }
+            std::vector<UnitTask> units;
             size_t a = 0;
             while (a < list.size()) {
                 size_t e = a;
                 int64_t bytes = 0;
                 while (e < list.size() && bytes < UNIT_BYTES) {
-                    bytes += (int64_t)list[e]->ncols * lt.P * (int64_t)fmt_size(list[e]->fmt);
+                    const int64_t b = (int64_t)list[e].ncols * lt.P * (int64_t)fmt_size(list[e].fmt);
+                    if (e > a && bytes + b > UNIT_BYTES + UNIT_BYTES / 2) break;
+                    bytes += b;
                     ++e;
                 }
                 UnitTask ut{};
@@ -1018,27 +1100,39 @@ static void build_tasks(hh_handle* h) {
                 ut.rb = (int32_t)S.uruns.size();
                 for (int f = 0; f < 4; ++f) {
                     for (size_t i = a; i < e; ++i)
-                        if (list[i]->fmt == f) S.uruns.push_back(*list[i]);
+                        if (list[i].fmt == f) S.uruns.push_back(list[i]);
                     ut.fe[f] = (int32_t)S.uruns.size();
                 }
                 ut.hid = 0;
-                S.unit.push_back(ut);
+                units.push_back(ut);
                 po += lt.P;
                 ft.nu++;
                 a = e;
             }
+            by_leaf.push_back(units);
             S.fin.push_back(ft);
         }
         h->part_rows = std::max(h->part_rows, po);
+        // dispatch order: unit k of every leaf (Morton order), then unit k + 1,
+        // so that waves running together read neighbouring rows of the same runs
+        for (size_t k = 0;; ++k) {
+            bool any = false;
+            for (const auto& units : by_leaf)
+                if (k < units.size()) {
+                    S.unit.push_back(units[k]);
+                    any = true;
+                }
+            if (!any) break;
+        }
     }
     for (TaskSet* S : {&F, &T}) {
         S->d_dot = upload(h->mem, S->dot);
         S->d_leaf = upload(h->mem, S->leaf);
+        S->d_runs = upload(h->mem, S->runs);
+        S->d_cl_run = upload(h->mem, S->cl_run);
         S->d_unit = upload(h->mem, S->unit);
         S->d_uruns = upload(h->mem, S->uruns);
         S->d_fin = upload(h->mem, S->fin);
-        S->d_runs = upload(h->mem, S->runs);
-        S->d_cl_run = upload(h->mem, S->cl_run);
         S->d_druns = S->druns.empty() ? nullptr : upload(h->mem, S->druns);
         S->d_cl_drun = S->cl_drun.empty() ? nullptr : upload(h->mem, S->cl_drun);
     }

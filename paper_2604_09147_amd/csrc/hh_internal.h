@@ -71,6 +71,7 @@ struct Desc {
 
 // Inner products of stored columns with a slice of the gathered vector:
 // tb[toff + c] = sum_j col_c[j] xt[xoff + j]  for c < ncols, j < P.
+// The coefficient carries the block's factor scales: tb = 2^exp (col . xt).
 struct DotTask {
     const void* col0;        // first element of column 0; column c starts c * P later
     int64_t xoff;            // padded row offset of the slice of xt
@@ -79,19 +80,23 @@ struct DotTask {
     int32_t ncols;
     int32_t fmt;             // HH_FMT_*
     int32_t hid;             // handle index in a batched launch
+    int32_t exp;             // eU + eV (power-of-two factor scales, exact)
+    int32_t pad_;
 };
 
-// The columns of one stored block restricted to the rows of a cluster (the
-// block's row cluster; for the transpose, its column cluster). Applied to a
-// leaf inside the cluster: y_leaf += 2^exp sum_c col_c[leaf rows] coef_c with
-// coef_c = tb[toff + c] (low-rank block) or xt[toff + c] (dense block).
+// Columns stored with a common stride and consecutive coefficients, restricted
+// to the rows of a cluster: the columns of one block, or of several blocks of
+// the same cluster and format stored one after another (their factors are
+// laid out that way). Applied to a leaf inside the cluster:
+// y_leaf += sum_c col_c[leaf rows] coef_c with coef_c = tb[toff + c]
+// (low-rank, scales already in tb) or xt[toff + c] (dense block).
 struct Run {
     const void* base;        // element (cluster row 0, column 0)
     int64_t pc;              // padded offset of the cluster's first row
     int32_t stride;          // elements between consecutive columns
     int32_t toff;
     int32_t ncols;
-    int16_t exp;             // eU + eV
+    int16_t pad_;
     int8_t fmt;              // HH_FMT_*; dense blocks are HH_FMT_FP64
     int8_t from_x;
 };
@@ -147,7 +152,8 @@ struct BlockRec {
     const void* u_ptr = nullptr;      // stored factors (format fmt), padded-row layout
     const void* v_ptr = nullptr;
     const double* d_ptr = nullptr;    // dense block, PI x n column-major
-    int64_t col = -1;                 // coefficient index of column 0
+    int64_t col = -1;                 // coefficient index of column 0 (product with H)
+    int64_t col_t = -1;               // coefficient index of column 0 (product with H^T)
     int64_t PI = 0, PJ = 0;           // padded lengths of row / column clusters
     int64_t pI = 0, pJ = 0;           // padded offsets of row / column clusters
 };

@@ -172,16 +172,15 @@ __global__ void gather_kernel(Desc d, const Desc* descs, int R) {
 }
 
 // --------------------------------------------------------------------- dot
-constexpr int XLDS = 4096;   // rows of xt staged in LDS for single-vector tasks
 
 // One iteration of a wave covers UC columns x UR pieces of 256 rows (UC UR =
 // NU, eight loads of 16 bytes per lane; four of 32 bytes for fp64).
 // Units past the last column or row re-read an in-bounds element and are
 // discarded (column clamped, weight zero), so every load is unconditional.
-template <int FMT, int UR>
+template <int FMT, int UR, int NU = 8>
 __device__ void dot_r1(const DotTask& t, const double* xg, const double* xs, bool lds,
                        double* tb, int wave, int lane) {
-    constexpr int UC = (FMT == HH_FMT_FP64 ? 4 : 8) / UR;
+    constexpr int UC = (FMT == HH_FMT_FP64 ? NU / 2 : NU) / UR;
     using acc_t = typename std::conditional<(FMT >= HH_FMT_FP16), float, double>::type;
     const int P = t.P;
     for (int c0 = wave * UC; c0 < t.ncols; c0 += 4 * UC) {
@@ -223,41 +222,50 @@ __device__ void dot_r1(const DotTask& t, const double* xg, const double* xs, boo
         }
 #pragma unroll
         for (int uc = 0; uc < UC; ++uc) {
-            const double s = wave_sum((double)a[uc]);
+            const double s = ldexp(wave_sum((double)a[uc]), t.exp);
             if (lane == 0 && c0 + uc < t.ncols) stg<double>(tb + t.toff + c0 + uc, s);
         }
     }
 }
 
-template <int FMT>
+template <int FMT, int NU>
 __device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs, bool lds,
                            double* tb, int wave, int lane) {
+    constexpr int NF = FMT == HH_FMT_FP64 ? NU / 2 : NU;   // loads of 16 bytes per lane
     const int nb = (t.P + 255) / 256;
-    if (nb <= 1) dot_r1<FMT, 1>(t, xg, xs, lds, tb, wave, lane);
-    else if (nb <= 2) dot_r1<FMT, 2>(t, xg, xs, lds, tb, wave, lane);
-    else if (nb <= 4 || FMT == HH_FMT_FP64) dot_r1<FMT, 4>(t, xg, xs, lds, tb, wave, lane);
-    else dot_r1<FMT, (FMT == HH_FMT_FP64 ? 4 : 8)>(t, xg, xs, lds, tb, wave, lane);
+    constexpr int R2 = NF < 2 ? NF : 2, R4 = NF < 4 ? NF : 4, R8 = NF < 8 ? NF : 8;
+    if (nb <= 1) dot_r1<FMT, 1, NU>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 2) dot_r1<FMT, R2, NU>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 4) dot_r1<FMT, R4, NU>(t, xg, xs, lds, tb, wave, lane);
+    else dot_r1<FMT, R8, NU>(t, xg, xs, lds, tb, wave, lane);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void dot1_kernel(Desc d, const Desc* descs,
-                                                   const DotTask* tasks) {
-    __shared__ double xs[XLDS];
+template <int NU, int XL>
+__device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks) {
+    __shared__ double xs[XL];
     const DotTask t = ldrec<DotTask>(tasks + blockIdx.x);
     const Desc D = descs ? ldrec<Desc>(descs + t.hid) : d;
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const double* x = D.xt + t.xoff;
-    const bool lds = t.P <= XLDS;
+    const bool lds = t.P <= XL;
     if (lds) {
         for (int i = threadIdx.x; i < t.P; i += 256) xs[i] = ldg<double>(x + i);
         __syncthreads();
     }
     switch (t.fmt) {
-        case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64>(t, x, xs, lds, D.tb, wave, lane); break;
-        case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32>(t, x, xs, lds, D.tb, wave, lane); break;
-        case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16>(t, x, xs, lds, D.tb, wave, lane); break;
-        default: dot_r1_any<HH_FMT_BF16>(t, x, xs, lds, D.tb, wave, lane); break;
+        case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+        case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+        case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+        default: dot_r1_any<HH_FMT_BF16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
     }
 }
+
+#define HH_DOT1_KERNEL(NAME, NU, XL, W)                                                         \
+    __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void NAME(         \
+        Desc d, const Desc* descs, const DotTask* tasks) {                                      \
+        dot1_body<NU, XL>(d, descs, tasks);                                                     \
+    }
+HH_DOT1_KERNEL(dot1_kernel, 8, 4096, 4)
 
 // Several right-hand sides, RC at a time (columns re-read per chunk of RC).
 template <int FMT, int RC>
@@ -284,7 +292,7 @@ __device__ void dot_rn(const DotTask& t, const double* xt, double* tb, int R, in
             }
 #pragma unroll
             for (int k = 0; k < RC; ++k) {
-                const double s = wave_sum((double)a[k]);
+                const double s = ldexp(wave_sum((double)a[k]), t.exp);
                 if (lane == 0 && k < nr) stg<double>(tb + (t.toff + c) * R + r0 + k, s);
             }
         }
@@ -311,49 +319,69 @@ __global__ __launch_bounds__(256) void dotn_kernel(Desc d, const Desc* descs,
 // groups of lps lanes (short leaves) and group g takes columns g, g + G, ...;
 // without SPLIT the column index and so the coefficient address are
 // wave-uniform.
-template <int FMT, int RC, bool SPLIT>
-__device__ inline void apply_run(const Run& rn, rsrc_t rs, uint32_t voff, const double* coef,
-                                 int R, int r0, int nr, int g, int G, double acc[4][RC]) {
-    constexpr int U = RC > 1 ? 2 : (SPLIT || FMT == HH_FMT_FP64) ? 8 : 16;
+// UB columns c, c + step, ... of one run (columns past the last one, only
+// when CLAMP, re-read the last column with weight zero).
+template <int FMT, int RC, int UB, bool CLAMP, bool SPLIT>
+__device__ inline void apply_cols(const Run& rn, rsrc_t rs, uint32_t voff, const double* coef,
+                                  int R, int r0, int nr, int c, int step, double ra[4][RC]) {
     const int n = rn.ncols;
-    const int step = SPLIT ? G : 1;
-    double ra[4][RC];
+    Raw4<FMT> raw[UB];
+    double cf[UB][RC];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int u = 0; u < UB; ++u) {
+        const int cu = c + u * step;
+        const int cc = CLAMP ? (cu < n ? cu : n - 1) : cu;
+        raw[u] = bload4<FMT>(rs, voff + (uint32_t)cc * (uint32_t)rn.stride * elem_bytes<FMT>());
+        const double* cp = coef + ((int64_t)rn.toff + cc) * R + r0;
 #pragma unroll
-        for (int k = 0; k < RC; ++k) ra[q][k] = 0.0;
-    for (int c = SPLIT ? g : 0; c < n; c += U * step) {
-        Raw4<FMT> raw[U];
-        double cf[U][RC];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int cu = c + u * step;
-            const int cc = cu < n ? cu : n - 1;
-            raw[u] = bload4<FMT>(rs, voff + (uint32_t)cc * (uint32_t)rn.stride * elem_bytes<FMT>());
-            const double* cp = coef + ((int64_t)rn.toff + cc) * R + r0;
-#pragma unroll
-            for (int k = 0; k < RC; ++k) {
-                const double* ck = cp + (k < nr ? k : 0);
-                cf[u][k] = SPLIT ? ldg<double>(ck) : ldc<double>(ck);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = c + u * step < n;
-            double v[4];
-            widen4<FMT, double>(raw[u], v);
-#pragma unroll
-            for (int k = 0; k < RC; ++k) {
-                const double w = (ok && k < nr) ? cf[u][k] : 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) ra[q][k] = fma(v[q], w, ra[q][k]);
-            }
+        for (int k = 0; k < RC; ++k) {
+            const double* ck = cp + (k < nr ? k : 0);
+            cf[u][k] = SPLIT ? ldg<double>(ck) : ldc<double>(ck);
         }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int u = 0; u < UB; ++u) {
+        const bool ok = !CLAMP || c + u * step < n;
+        double v[4];
+        widen4<FMT, double>(raw[u], v);
 #pragma unroll
-        for (int k = 0; k < RC; ++k) acc[q][k] += ldexp(ra[q][k], rn.exp);
+        for (int k = 0; k < RC; ++k) {
+            const double w = (ok && k < nr) ? cf[u][k] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ra[q][k] = fma(v[q], w, ra[q][k]);
+        }
+    }
+}
+
+// Apply one run to a lane's 4 rows: acc += sum_c col_c[rows] coef_c. Columns
+// go in batches of U, then
+// U/2 and U/4, and a clamped batch for the last few, so that short runs do
+// not issue loads of absent columns. SPLIT: the wave is cut into G groups of
+// lps lanes (short leaves) and group g takes columns g, g + G, ...; without
+// SPLIT the column index and so the coefficient address are wave-uniform.
+template <int FMT, int RC, bool SPLIT, int UB = 16>
+__device__ inline void apply_run(const Run& rn, rsrc_t rs, uint32_t voff, const double* coef,
+                                 int R, int r0, int nr, int g, int G, double acc[4][RC]) {
+    constexpr int U = RC > 1 ? 2 : SPLIT ? 4 : FMT == HH_FMT_FP64 ? (UB < 8 ? UB : 8) : UB;
+    const int n = rn.ncols;
+    const int step = SPLIT ? G : 1;
+    int c = SPLIT ? g : 0;
+    for (; c + (U - 1) * step < n; c += U * step)
+        apply_cols<FMT, RC, U, false, SPLIT>(rn, rs, voff, coef, R, r0, nr, c, step, acc);
+    if constexpr (U >= 8) {
+        if (c + (U / 2 - 1) * step < n) {
+            apply_cols<FMT, RC, U / 2, false, SPLIT>(rn, rs, voff, coef, R, r0, nr, c, step, acc);
+            c += (U / 2) * step;
+        }
+    }
+    if constexpr (U >= 16) {
+        if (c + (U / 4 - 1) * step < n) {
+            apply_cols<FMT, RC, U / 4, false, SPLIT>(rn, rs, voff, coef, R, r0, nr, c, step, acc);
+            c += (U / 4) * step;
+        }
+    }
+    constexpr int T = U >= 16 ? U / 4 : U >= 8 ? U / 2 : U;
+    if (c < n) apply_cols<FMT, RC, T, true, SPLIT>(rn, rs, voff, coef, R, r0, nr, c, step, acc);
 }
 
 // Index of the cluster of level l that contains leaf box `leaf`: clusters are
@@ -508,32 +536,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
 // factor data), so that the hardware dispatcher balances leaves of unequal
 // work. Each unit writes its partial sum of the leaf's rows; the finishing
 // kernel adds a leaf's partials in unit order.
-template <int F, bool SPLIT>
+template <int F, bool SPLIT, int UB>
 __device__ inline void unit_runs_fmt(const Desc& D, const UnitTask& ut, int b, int e, int64_t row,
                                      int g, int G, double acc[4][1]) {
     constexpr uint32_t es = elem_bytes<F>();
+    if (b >= e) return;
+    Run rn = ldrec<Run>(D.uruns + b);
     for (int i = b; i < e; ++i) {
-        const Run rn = ldrec<Run>(D.uruns + i);
+        // the next record is requested before this run's factor loads
+        const Run nx = ldrec<Run>(D.uruns + (i + 1 < e ? i + 1 : i));
         const double* coef = rn.from_x ? D.xt : D.tb;
         const int64_t off = ut.poff - rn.pc;
         const rsrc_t rs = make_rsrc(static_cast<const char*>(rn.base) + off * es,
                                     ((int64_t)rn.ncols * rn.stride - off) * es);
-        apply_run<F, 1, SPLIT>(rn, rs, (uint32_t)row * es, coef, 1, 0, 1, g, G, acc);
+        apply_run<F, 1, SPLIT, UB>(rn, rs, (uint32_t)row * es, coef, 1, 0, 1, g, G, acc);
+        rn = nx;
     }
 }
 
-template <bool SPLIT>
+template <bool SPLIT, int UB>
 __device__ inline void unit_runs(const Desc& D, const UnitTask& ut, int64_t row, int g, int G,
                                  double acc[4][1]) {
-    unit_runs_fmt<HH_FMT_FP64, SPLIT>(D, ut, ut.rb, ut.fe[0], row, g, G, acc);
-    unit_runs_fmt<HH_FMT_FP32, SPLIT>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc);
-    unit_runs_fmt<HH_FMT_FP16, SPLIT>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc);
-    unit_runs_fmt<HH_FMT_BF16, SPLIT>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc);
+    unit_runs_fmt<HH_FMT_FP64, SPLIT, UB>(D, ut, ut.rb, ut.fe[0], row, g, G, acc);
+    unit_runs_fmt<HH_FMT_FP32, SPLIT, UB>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc);
+    unit_runs_fmt<HH_FMT_FP16, SPLIT, UB>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc);
+    unit_runs_fmt<HH_FMT_BF16, SPLIT, UB>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc);
 }
 
 // Four units per workgroup, one per wave; the waves never synchronise.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void unit_kernel(
-    Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {
+template <int UB>
+__device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int64_t ui = (int64_t)blockIdx.x * 4 + wave;
     if (ui >= nunits) return;
@@ -548,8 +580,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void u
         const int prow = jlo + 4 * sl;
         const int64_t row = prow < P ? prow : 0;     // clamped: in bounds, never written
         double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
-        if (G == 1) unit_runs<false>(D, ut, row, 0, 1, acc);
-        else unit_runs<true>(D, ut, row, g, G, acc);
+        if (G == 1) unit_runs<false, UB>(D, ut, row, 0, 1, acc);
+        else unit_runs<true, UB>(D, ut, row, g, G, acc);
         for (int off = lps; off < 64; off <<= 1)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q][0] += __shfl_xor(acc[q][0], off, 64);
@@ -559,6 +591,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void u
                 if (prow + q < P) stg<double>(D.part + ut.po + prow + q, acc[q][0]);
     }
 }
+
+#define HH_UNIT_KERNEL(NAME, UB, W)                                                          \
+    __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void NAME(         \
+        Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {                    \
+        unit_body<UB>(d, descs, units, nunits);                                                 \
+    }
+HH_UNIT_KERNEL(unit_kernel, 16, 4)
 
 // y rows of one leaf: its units' partials in order, then (transpose) the
 // transposed dense blocks; written in caller order. Lane l owns rows 4l..4l+3
