@@ -1,0 +1,145 @@
+"""GPU tests of the differentiable product (transpose as backward), the
+batched launch over many handles and handles derived from a uniform fp64 one,
+all through the C ABI.
+
+Bars as in the parity tests: 1e-2 tol (relative 2-norm) against the oracle's
+own H^ product, 10 tol against the dense kernel product, with the fp32 io
+floor 2^-22 for fp32 inputs and outputs."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hh_oracle as O
+from parity_util import build_pair, compare_structure, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _double_layer_problem(n, seed):
+    rng = np.random.default_rng(seed)
+    P = np.concatenate([W.sphere_surface(n // 2, 3, rng), W.ball_interior(n - n // 2, 3, rng)])
+    return P, W.unit_normals(n, 3, rng)
+
+
+def test_autograd_backward_is_the_transposed_product():
+    # nonsymmetric double-layer kernel, sphere + ball, 16 fp32 right-hand sides
+    torch = _torch()
+    from paper_2604_09147_amd import HMatrix
+    from paper_2604_09147_amd.autograd import hh_apply
+    tol = 1e-6
+    P, nrm = _double_layer_problem(3000, 505)
+    g, o = build_pair(P, W.DOUBLE_LAYER, tol, 1.5, -1, 64, normals=nrm, io="f32")
+    compare_structure(g, o)
+    rng = np.random.default_rng(7)
+    x = torch.from_numpy(rng.standard_normal((3000, 16))).float().cuda().requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((3000, 16))).float().cuda()
+    y = hh_apply(g, x)
+    (y * w).sum().backward()
+    grad = x.grad.double().cpu().numpy()
+    wd = w.double().cpu().numpy()
+    k = O.Kernel(W.DOUBLE_LAYER, normals=nrm)
+    bar = max(1e-2 * tol, 2.0 ** -22)
+    assert rel(grad, O.matvec_t(o, wd)) <= bar
+    assert rel(grad, O.dense_matvec_t(P, k, wd)) <= 10 * tol
+    # the forward pass is the product itself
+    assert rel(y.detach().double().cpu().numpy(), O.matvec(o, x.detach().double().cpu().numpy())) <= bar
+
+    # finite differences of f(x) = <w, H^ x> in fp64 (step 1e-3): with fp64 /
+    # fp32 storage the product is computed in fp64, f is linear, and the
+    # central difference equals <H^T w, e> up to rounding
+    g64 = HMatrix(P, W.DOUBLE_LAYER, tol, 1.5, -1, 64, normals=nrm, mask=0x3)
+    x64 = torch.from_numpy(rng.standard_normal(3000)).cuda()
+    w64 = torch.from_numpy(rng.standard_normal(3000)).cuda()
+    xr = x64.clone().requires_grad_(True)
+    (hh_apply(g64, xr) * w64).sum().backward()
+    for t in range(3):
+        e = torch.from_numpy(rng.standard_normal(3000)).cuda()
+        h = 1e-3
+        fp = float((g64.matvec(x64 + h * e) * w64).sum())
+        fm = float((g64.matvec(x64 - h * e) * w64).sum())
+        fd = (fp - fm) / (2 * h)
+        an = float((xr.grad * e).sum())
+        assert abs(fd - an) <= 1e-9 * max(abs(an), 1.0), (fd, an)
+    g64.free()
+
+
+def test_transpose_adjoint_identity():
+    # <w, H^ x> = <H^^T w, x> with the same stored factors (fp64 arithmetic)
+    torch = _torch()
+    from paper_2604_09147_amd import HMatrix
+    P, nrm = _double_layer_problem(5000, 11)
+    g = HMatrix(P, W.DOUBLE_LAYER, 1e-6, 1.5, -1, 64, normals=nrm, mask=0x3)
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy(rng.standard_normal(5000)).cuda()
+    w = torch.from_numpy(rng.standard_normal(5000)).cuda()
+    a = float((w * g.matvec(x)).sum())
+    b = float((g.matvec_t(w) * x).sum())
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0), (a, b)
+    g.free()
+
+
+def test_batched_launch_equals_individual_products():
+    # uneven instances of the batched workload: Gaussian kernels, log-uniform
+    # sizes, mixed tolerances, fp32 io; one launch per phase over all handles
+    torch = _torch()
+    from paper_2604_09147_amd import HMatrix, matvec_batch
+    rng = np.random.default_rng(404)
+    mats, xs, probs = [], [], []
+    for t in range(6):
+        n = int(2 ** rng.uniform(10, 13))
+        P = rng.random((n, 3))
+        h = float(rng.uniform(0.05, 0.3))
+        tol = float(rng.choice([1e-4, 1e-6, 1e-8]))
+        m = HMatrix(P, W.GAUSS, tol, math.sqrt(3), -1, 64, h=h, io_dtype="f32")
+        mats.append(m)
+        probs.append((P, h, tol))
+        xs.append(torch.from_numpy(rng.standard_normal(n)).float().cuda())
+    ys = matvec_batch(mats, xs)
+    torch.cuda.synchronize()
+    for m, x, y in zip(mats, xs, ys):
+        yi = m.matvec(x)
+        assert torch.equal(y, yi), "batched product differs from the single product"
+    # the smallest instance against the oracle and the dense product
+    i = int(np.argmin([p[0].shape[0] for p in probs]))
+    P, h, tol = probs[i]
+    o = O.build(P, O.Kernel(W.GAUSS, h=h), tol, math.sqrt(3), -1, 64)
+    compare_structure(mats[i], o)
+    xin = xs[i].double().cpu().numpy()
+    y = ys[i].double().cpu().numpy()
+    bar = max(1e-2 * tol, 2.0 ** -22)
+    assert rel(y, O.matvec(o, xin)) <= bar
+    assert rel(y, O.dense_matvec(P, O.Kernel(W.GAUSS, h=h), xin)) <= max(10 * tol, 2.0 ** -22)
+    for m in mats:
+        m.free()
+
+
+def test_derived_handle_equals_direct_build():
+    # Alg. 3 applied to the fp64 factors of a uniform handle gives the handle a
+    # direct adaptive build gives (same tree, partition, ranks, formats, rounding)
+    torch = _torch()
+    from paper_2604_09147_amd import HMatrix
+    rng = np.random.default_rng(21)
+    P = rng.random((6000, 3))
+    g64 = HMatrix(P, W.INV_R, 1e-5, 1.5, -1, 64, uniform_fp64=True)
+    ga = g64.derive(mask=0xF)
+    gd = HMatrix(P, W.INV_R, 1e-5, 1.5, -1, 64)
+    ba, bd = ga.blocks(), gd.blocks()
+    for key in ("level", "box_i", "box_j", "rank", "format"):
+        assert np.array_equal(ba[key], bd[key]), key
+    assert np.all(g64.blocks()["format"][g64.blocks()["lowrank"].astype(bool)] == W.FMT_FP64)
+    x = torch.from_numpy(rng.standard_normal(6000)).cuda()
+    ya, yd = ga.matvec(x), gd.matvec(x)
+    assert float(torch.linalg.norm(ya - yd) / torch.linalg.norm(yd)) <= 1e-15
+    y64 = g64.matvec(x)
+    assert float(torch.linalg.norm(ya - y64) / torch.linalg.norm(y64)) <= 1e-5
+    for m in (ga, gd, g64):
+        m.free()
