@@ -189,8 +189,9 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
 
-    names = ["gather", "column inner products", "leaf accumulation"]
-    kernels = ["gather_kernel", "dot1_kernel", "accum_kernel"]
+    names = ["gather", "column inner products (dot1_kernel)",
+             "leaf accumulation (unit_kernel + finish_kernel)"]
+    kernels = ["gather_kernel", "dot1_kernel", "accumulation"]
     k = int(np.argmax(ph_a))
     achieved = sa["phase_bytes"][k] / (ph_a[k] / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1),
