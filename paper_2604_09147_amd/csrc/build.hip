@@ -970,6 +970,18 @@ static void build_tasks(hh_handle* h) {
                 t.exp = r.eU + r.eV;
                 (pass == 0 ? F : T).dot.push_back(t);
             }
+            for (int64_t c0 = 0; c0 < r.rank; c0 += 16 * DOTM_MT) {
+                DotTask t{};
+                t.col0 = base + (size_t)(c0 * Pl) * es;
+                t.xoff = pass == 0 ? r.pJ : r.pI;
+                t.toff = (pass == 0 ? r.col : r.col_t) + c0;
+                t.P = (int32_t)Pl;
+                t.ncols = (int32_t)std::min<int64_t>(16 * DOTM_MT, r.rank - c0);
+                t.fmt = r.fmt;
+                t.hid = 0;
+                t.exp = r.eU + r.eV;
+                (pass == 0 ? F : T).dotm.push_back(t);
+            }
         }
     }
     // clusters in (level, box) order; cluster (l, b) has index
@@ -978,11 +990,37 @@ static void build_tasks(hh_handle* h) {
     for (int l = 0; l <= L; ++l) first[l + 1] = first[l] + ((int64_t)1 << (d * l));
     const int64_t ncl = first[L + 1];
     const int64_t nleaf = (int64_t)1 << (d * L);
+    // transposed copies of the dense blocks: the product with H^T applies them
+    // as ordinary runs of the column cluster
+    {
+        int64_t total = 0;
+        for (const auto& r : h->blocks)
+            if (!r.lowrank) total += r.PJ * (r.b.ie - r.b.ib);
+        double* DT = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(total, 1) * 8 + 256, true));
+        std::vector<TransItem> items;
+        int64_t off = 0, maxcount = 0;
+        for (auto& r : h->blocks) {
+            if (r.lowrank) continue;
+            const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
+            r.dt_ptr = DT + off;
+            items.push_back(TransItem{r.d_ptr, DT + off, m, n, r.PI, r.PJ});
+            maxcount = std::max(maxcount, m * n);
+            off += r.PJ * m;
+        }
+        for (size_t a = 0; a < items.size(); a += 32768) {
+            const size_t e = std::min(items.size(), a + 32768);
+            std::vector<TransItem> part(items.begin() + a, items.begin() + e);
+            DevMem tmp;
+            TransItem* d_items = upload(tmp, part);
+            launch_transpose(d_items, (int)part.size(), maxcount, nullptr);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipDeviceSynchronize());
+        }
+    }
     for (int dir = 0; dir < 2; ++dir) {
         TaskSet& S = dir == 0 ? F : T;
         const std::vector<int64_t>& ord = dir == 0 ? ord_f : ord_t;
         std::vector<std::vector<Run>> per(ncl);
-        std::vector<std::vector<DotRun>> dper(dir == 1 ? nleaf : 0);
         for (int64_t bi : ord) {
             const BlockRec& r = h->blocks[bi];
             const int64_t box = dir == 0 ? r.b.bi : r.b.bj;
@@ -1006,14 +1044,13 @@ static void build_tasks(hh_handle* h) {
                 rn.fmt = HH_FMT_FP64;
                 rn.from_x = 1;
             } else {
-                if (r.b.level != L) fail(HH_EINTERNAL, "dense block above the leaf level");
-                DotRun dr{};
-                dr.base = r.d_ptr;
-                dr.xoff = r.pI;
-                dr.P = (int32_t)r.PI;
-                dr.ncols = (int32_t)(r.b.je - r.b.jb);
-                dper[r.b.bj].push_back(dr);
-                continue;
+                rn.base = r.dt_ptr;
+                rn.pc = r.pJ;
+                rn.stride = (int32_t)r.PJ;
+                rn.toff = (int32_t)r.pI;
+                rn.ncols = (int32_t)(r.b.ie - r.b.ib);
+                rn.fmt = HH_FMT_FP64;
+                rn.from_x = 1;
             }
             // merge with the previous run when the columns continue it
             std::vector<Run>& lst = per[ci];
@@ -1038,13 +1075,6 @@ static void build_tasks(hh_handle* h) {
                     if (rn.fmt == f) S.runs.push_back(rn);
             }
         S.cl_run[4 * ncl] = (int32_t)S.runs.size();
-        if (dir == 1) {
-            S.cl_drun.assign(nleaf + 1, 0);
-            for (int64_t b = 0; b < nleaf; ++b) {
-                S.druns.insert(S.druns.end(), dper[b].begin(), dper[b].end());
-                S.cl_drun[b + 1] = (int32_t)S.druns.size();
-            }
-        }
         for (int64_t lf = 0; lf < nleaf; ++lf) {
             if (h->leaf_psz[lf] == 0) continue;
             LeafTask lt{};
@@ -1125,16 +1155,23 @@ static void build_tasks(hh_handle* h) {
             if (!any) break;
         }
     }
+    // several-RHS tiles ordered by the cluster of x they read (column cluster
+    // for H, row cluster for H^T), so that x_J stays in L2 across its blocks
+    for (int dir = 0; dir < 2; ++dir) {
+        std::vector<DotTask>& v = (dir == 0 ? F : T).dotm;
+        std::stable_sort(v.begin(), v.end(), [](const DotTask& a, const DotTask& b) {
+            return std::make_tuple(a.P, a.xoff) < std::make_tuple(b.P, b.xoff);
+        });
+    }
     for (TaskSet* S : {&F, &T}) {
         S->d_dot = upload(h->mem, S->dot);
+        S->d_dotm = upload(h->mem, S->dotm);
         S->d_leaf = upload(h->mem, S->leaf);
         S->d_runs = upload(h->mem, S->runs);
         S->d_cl_run = upload(h->mem, S->cl_run);
         S->d_unit = upload(h->mem, S->unit);
         S->d_uruns = upload(h->mem, S->uruns);
         S->d_fin = upload(h->mem, S->fin);
-        S->d_druns = S->druns.empty() ? nullptr : upload(h->mem, S->druns);
-        S->d_cl_drun = S->cl_drun.empty() ? nullptr : upload(h->mem, S->cl_drun);
     }
 }
 

@@ -59,8 +59,6 @@ static Desc make_desc(const hh_handle* h, const TaskSet& S, const void* x, void*
     d.cl_run = S.d_cl_run;
     d.uruns = S.d_uruns;
     d.part = h->part;
-    d.druns = S.d_druns;
-    d.cl_drun = S.d_cl_drun;
     d.np = h->np;
     d.io = h->opt.io_dtype;
     d.d = h->plan.d;
@@ -87,7 +85,8 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     }
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
-    launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
+    if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
+    else launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[2], (hipStream_t)stream));
     if (R == 1)
         launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(), stream);
@@ -128,7 +127,7 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
         ensure_workspace(h, nrhs);
         descs[t] = make_desc(h, h->fwd, x[t], y[t]);
         max_np = std::max(max_np, h->np);
-        for (DotTask k : h->fwd.dot) {
+        for (DotTask k : (nrhs == 1 ? h->fwd.dot : h->fwd.dotm)) {
             k.hid = t;
             dot.push_back(k);
         }

@@ -21,23 +21,21 @@ struct DevMem {
 
 struct TaskSet {                      // one direction of the product
     std::vector<DotTask> dot;
+    std::vector<DotTask> dotm;        // tiles of at most 16 columns (several RHS)
     std::vector<LeafTask> leaf;
     std::vector<UnitTask> unit;       // single-vector work units, leaf by leaf
     std::vector<Run> uruns;           // their runs, format-grouped per unit
     std::vector<FinishTask> fin;      // one per nonempty leaf
     std::vector<Run> runs;            // grouped by cluster, clusters in (level, box) order
     std::vector<int32_t> cl_run;      // 4 (sum_l 2^(d l)) + 1 boundaries (cluster, format)
-    std::vector<DotRun> druns;        // grouped by leaf box
-    std::vector<int32_t> cl_drun;     // 2^(d L) + 1 leaf boundaries (empty: no druns)
     DotTask* d_dot = nullptr;
+    DotTask* d_dotm = nullptr;
     LeafTask* d_leaf = nullptr;
     UnitTask* d_unit = nullptr;
     Run* d_uruns = nullptr;
     FinishTask* d_fin = nullptr;
     Run* d_runs = nullptr;
     int32_t* d_cl_run = nullptr;
-    DotRun* d_druns = nullptr;
-    int32_t* d_cl_drun = nullptr;
 };
 
 }  // namespace hh

@@ -87,6 +87,15 @@ struct JacItem {
     double* sigma;       // s out, decreasing
 };
 
+// Transposed copy of a dense block: dst (rows n, ld_dst) = src^T for the
+// m x n column-major src (ld_src); rows n .. ld_dst of dst stay zero.
+struct TransItem {
+    const double* src;
+    double* dst;
+    int64_t m, n;
+    int64_t ld_src, ld_dst;
+};
+
 struct PackItem {
     const double* src;
     void* dst;
@@ -111,6 +120,7 @@ void launch_rank(RankItem* items, int nitems, double eps2, hipStream_t s);
 void launch_finalize(const FinItem* items, int nitems, const int64_t* tpad, hipStream_t s);
 void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s);
 void launch_pack(const PackItem* items, int nitems, int64_t max_count, hipStream_t s);
+void launch_transpose(const TransItem* items, int nitems, int64_t max_count, hipStream_t s);
 void launch_house_qr(double* A, int64_t ld, int64_t strideA, double* tau, int64_t strideT,
                      int64_t m, int n, int nitems, hipStream_t st);
 void launch_panel_v(const double* A, int64_t ld, int64_t strideA, const double* tau,

@@ -46,7 +46,6 @@ void box_coords(int64_t box, int level, int d, int64_t* c);
 constexpr int ROW_PAD = 4;
 
 struct Run;
-struct DotRun;
 
 // Per-handle device pointers the product kernels need for one direction of the
 // product (passed by value, or as an array indexed by DotTask::hid /
@@ -61,8 +60,6 @@ struct Desc {
     const int32_t* cl_run;   // runs of cluster c in format f: [cl_run[4c + f], cl_run[4c + f + 1])
     const Run* uruns;        // runs of the single-vector work units
     double* part;            // partial sums of the work units
-    const DotRun* druns;     // transposed dense blocks by leaf (NULL: none)
-    const int32_t* cl_drun;  // druns of leaf box b: [cl_drun[b], cl_drun[b + 1])
     int64_t np;              // padded length
     int32_t io;              // HH_IO_F64 / HH_IO_F32
     int32_t d, L;            // dimension and depth of the tree
@@ -101,14 +98,6 @@ struct Run {
     int8_t from_x;
 };
 
-// Transposed dense block applied to leaf mu: y_mu[j] += dot(D[:, j], xt_lambda).
-struct DotRun {
-    const double* base;      // column 0 of the block (column-major, padded rows)
-    int64_t xoff;            // padded offset of lambda in xt
-    int32_t P;               // padded rows of lambda
-    int32_t ncols;           // real points of mu
-};
-
 // One nonempty leaf box (one wave of the accumulation kernel).
 struct LeafTask {
     int64_t poff;            // padded offset of the leaf
@@ -133,7 +122,7 @@ struct UnitTask {
 };
 
 // One leaf of the finishing kernel: y rows = sum over its nu units of
-// part[po + k P + row], plus the transposed dense blocks of the leaf.
+// part[po + k P + row].
 struct FinishTask {
     int64_t poff;
     int64_t po;
@@ -152,11 +141,15 @@ struct BlockRec {
     const void* u_ptr = nullptr;      // stored factors (format fmt), padded-row layout
     const void* v_ptr = nullptr;
     const double* d_ptr = nullptr;    // dense block, PI x n column-major
+    const double* dt_ptr = nullptr;   // its transpose, PJ x m column-major (product with H^T)
     int64_t col = -1;                 // coefficient index of column 0 (product with H)
     int64_t col_t = -1;               // coefficient index of column 0 (product with H^T)
     int64_t PI = 0, PJ = 0;           // padded lengths of row / column clusters
     int64_t pI = 0, pJ = 0;           // padded offsets of row / column clusters
 };
+
+// Columns per several-RHS phase-V tile: DOTM_MT MFMA tiles of 16 columns.
+constexpr int DOTM_MT = 1;
 
 // Kernel launch wrappers (defined in the .hip files).
 void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int R, void* stream);

@@ -710,6 +710,17 @@ __global__ void pack_kernel(const PackItem* items) {
     }
 }
 
+// One item per blockIdx.y; element (i, j) of src goes to (j, i) of dst.
+__global__ void transpose_kernel(const TransItem* items) {
+    const TransItem it = items[blockIdx.y];
+    const int64_t count = it.m * it.n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / it.m, i = e - j * it.m;      // src column j, row i
+        it.dst[i * it.ld_dst + j] = it.src[j * it.ld_src + i];
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
 void launch_gen(const KernelDev& k, const double* pts, const double* nrm, const int64_t* tpad,
@@ -765,6 +776,11 @@ void launch_svd_to_jac(const JacItem* items, const double* U, const double* Vt, 
 
 void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s) {
     hipLaunchKernelGGL(maxabs_kernel, dim3(nitems), dim3(256), 0, s, items, out);
+}
+
+void launch_transpose(const TransItem* items, int nitems, int64_t max_count, hipStream_t s) {
+    dim3 grid(grid_for(max_count, 4096), nitems);
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, items);
 }
 
 void launch_pack(const PackItem* items, int nitems, int64_t max_count, hipStream_t s) {

@@ -1,21 +1,24 @@
 // Product kernels of Alg. 4 on gfx950: b = sum_b U_b (V_b^T x_J) + sum D x.
 //
 // Phase 1 (gather):     xt = x in padded tree order (fp64).
-// Phase 2 (dot):        one coefficient per stored column, tb[c] = V_c . xt_J (for
-//                       the transpose, U_c . xt_I). One workgroup per task of
-//                       columns of one block; every wave keeps eight independent
-//                       4-row vector loads in flight (several columns of a short
-//                       column length, or several 256-row pieces of a long one).
-// Phase 3 (accumulate): one wave per leaf box owns that leaf's output rows. The
-//                       cluster containing the leaf at each level lists its runs
-//                       (the columns of one stored block, restricted to the
-//                       cluster's rows); the wave applies each run to its rows with
-//                       the coefficients tb[c] 2^e (low-rank) or xt (dense), then,
-//                       for the transpose, the transposed dense blocks, and writes
-//                       y in caller order. Run metadata and coefficients are
-//                       wave-uniform (scalar loads); only factor data moves through
-//                       the vector memory path. No atomics and a fixed order:
-//                       results are bitwise reproducible.
+// Phase 2 (dot):        one coefficient per stored column, tb[c] = 2^e V_c . xt_J
+//                       (for the transpose, U_c . xt_I), e the block's factor
+//                       scales. One workgroup per task of columns of one block;
+//                       every wave keeps eight independent 16-byte loads per lane
+//                       in flight (several columns of a short column length, or
+//                       several 256-row pieces of a long one).
+// Phase 3 (accumulate): the output rows of a leaf box are the sum, over the
+//                       clusters that contain the leaf (one per level), of runs:
+//                       strided column sets (the factors of the cluster's blocks
+//                       of one storage format, or a dense block) times their
+//                       coefficients tb (low-rank) or xt (dense). One RHS: each
+//                       leaf's runs are cut into work units of about 1 MB, one
+//                       wave each, writing partial rows that a finishing kernel
+//                       adds in unit order and writes to y in caller order.
+//                       Several RHS: one wave per leaf walks the cluster runs.
+//                       Run records and coefficients are wave-uniform (scalar
+//                       loads); factor data goes through buffer loads. No atomics
+//                       and a fixed order: results are bitwise reproducible.
 // Factors stored in fp32 / fp64 and dense blocks use fp64 arithmetic; fp16 and
 // bf16 inner products multiply and accumulate their lane partials in fp32.
 #include <hip/hip_runtime.h>
@@ -413,10 +416,9 @@ __device__ inline void apply_runs_fmt(const Desc& D, const LeafTask& lt, int64_t
 // Runs of the clusters containing the leaf at levels lmin..L; each cluster
 // lists its runs grouped by storage format.
 template <int RC, bool SPLIT>
-__device__ inline void apply_cluster_runs(const Desc& D, const LeafTask& lt, int lmin,
-                                          int64_t row, int R, int r0, int nr, int g, int G,
-                                          double acc[4][RC]) {
-    for (int l = lmin; l <= D.L; ++l) {
+__device__ inline void apply_cluster_runs(const Desc& D, const LeafTask& lt, int64_t row, int R,
+                                          int r0, int nr, int g, int G, double acc[4][RC]) {
+    for (int l = 0; l <= D.L; ++l) {
         const int64_t ci = cluster_index(D, l, lt.leaf);
         apply_runs_fmt<HH_FMT_FP64, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
         apply_runs_fmt<HH_FMT_FP32, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
@@ -425,52 +427,10 @@ __device__ inline void apply_cluster_runs(const Desc& D, const LeafTask& lt, int
     }
 }
 
-// Transposed dense blocks of leaf mu (column cluster mu at the leaf level):
-// y_mu[j] += D[:, j] . xt_lambda for the rows j of the strip [jlo, jlo + strip);
-// row j's sum goes to lane j / 4 (the lane that holds it after the combine).
+// The output rows of one leaf (several right-hand sides, RC per pass): runs
+// of the clusters that contain it, then the write of y.
 template <int RC>
-__device__ inline void add_transposed_dense(const Desc& D, int leaf, int jlo, int strip, int lane,
-                                            int R, int r0, int nr, double acc[4][RC]) {
-    const int db = ldc<int32_t>(D.cl_drun + leaf), de = ldc<int32_t>(D.cl_drun + leaf + 1);
-    for (int di = db; di < de; ++di) {
-        const DotRun dr = ldrec<DotRun>(D.druns + di);
-        const int jhi = dr.ncols < jlo + strip ? dr.ncols : jlo + strip;
-        for (int j = jlo; j < jhi; ++j) {
-            const double* col = dr.base + (int64_t)j * dr.P;
-            double a[RC];
-#pragma unroll
-            for (int k = 0; k < RC; ++k) a[k] = 0.0;
-            for (int i = 4 * lane; i < dr.P; i += 256) {
-                double v[4];
-                widen4<HH_FMT_FP64, double>(load4<HH_FMT_FP64>(col, i), v);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double* xr = D.xt + (dr.xoff + i + q) * R + r0;
-#pragma unroll
-                    for (int k = 0; k < RC; ++k)
-                        if (k < nr) a[k] = fma(v[q], ldg<double>(xr + k), a[k]);
-                }
-            }
-            const int jj = j - jlo;
-#pragma unroll
-            for (int k = 0; k < RC; ++k) {
-                const double s = wave_sum(a[k]);
-                if (lane == (jj >> 2))
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (q == (jj & 3)) acc[q][k] += s;
-            }
-        }
-    }
-}
-
-// The output rows of one leaf: runs of its clusters at levels lmin..L (the
-// levels above lmin already summed into init, which only a single-vector
-// product of a leaf of at most 256 rows passes), transposed dense blocks, and
-// the write of y.
-template <int RC>
-__device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R, int lmin,
-                          double i0, double i1, double i2, double i3) {
+__device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R) {
     const int P = lt.P;
     int lps = 1;
     while (lps < 64 && 4 * lps < P) lps <<= 1;  // lanes per column piece
@@ -486,18 +446,14 @@ __device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R, in
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < RC; ++k) acc[q][k] = 0.0;
-            if (jlo == 0 && r0 == 0 && g == 0) {
-                acc[0][0] = i0; acc[1][0] = i1; acc[2][0] = i2; acc[3][0] = i3;
-            }
-            if (G == 1) apply_cluster_runs<RC, false>(D, lt, lmin, row, R, r0, nr, 0, 1, acc);
-            else apply_cluster_runs<RC, true>(D, lt, lmin, row, R, r0, nr, g, G, acc);
+            if (G == 1) apply_cluster_runs<RC, false>(D, lt, row, R, r0, nr, 0, 1, acc);
+            else apply_cluster_runs<RC, true>(D, lt, row, R, r0, nr, g, G, acc);
             // groups covering the same rows, combined in a fixed order
             for (int off = lps; off < 64; off <<= 1)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int k = 0; k < RC; ++k) acc[q][k] += __shfl_xor(acc[q][k], off, 64);
-            if (D.cl_drun) add_transposed_dense<RC>(D, lt.leaf, jlo, strip, lane, R, r0, nr, acc);
             if (g == 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -528,7 +484,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
     if (li >= nleaves) return;
     const LeafTask lt = ldrec<LeafTask>(leaves + li);
     const Desc D = descs ? ldrec<Desc>(descs + lt.hid) : d;
-    leaf_wave<RC>(D, lt, lane, R, 0, 0.0, 0.0, 0.0, 0.0);
+    leaf_wave<RC>(D, lt, lane, R);
 }
 
 // ---------------------------------------------- single-vector work units
@@ -599,9 +555,8 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
     }
 HH_UNIT_KERNEL(unit_kernel, 16, 4)
 
-// y rows of one leaf: its units' partials in order, then (transpose) the
-// transposed dense blocks; written in caller order. Lane l owns rows 4l..4l+3
-// of each 256-row strip.
+// y rows of one leaf: its units' partials in unit order, written in caller
+// order. Lane l owns rows 4l..4l+3 of each 256-row strip.
 __global__ __launch_bounds__(256) void finish_kernel(Desc d, const Desc* descs,
                                                      const FinishTask* fin, int64_t nfin) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -619,7 +574,6 @@ __global__ __launch_bounds__(256) void finish_kernel(Desc d, const Desc* descs,
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[q][0] += ldg<double>(pp + q);
             }
-        if (D.cl_drun) add_transposed_dense<1>(D, ft.leaf, jlo, 256, lane, 1, 0, 1, acc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (prow + q >= P) continue;
@@ -630,6 +584,214 @@ __global__ __launch_bounds__(256) void finish_kernel(Desc d, const Desc* descs,
         }
     }
 }
+
+// ------------------------------------------- several right-hand sides: MFMA
+// v_mfma_f64_16x16x4f64: D (16 x 16) += A (16 x 4) B (4 x 16). Lane l holds
+// A[l & 15][l >> 4], B[l >> 4][l & 15] and D[4 r + (l >> 4)][l & 15] in its
+// register r. The reduction index K may be permuted freely as long as A and B
+// use the same permutation; both kernels below let a lane hold four
+// consecutive stored rows (one 16-byte load) and spend them on four MFMAs.
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline dbl4_t mfma16(double a, double b, dbl4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Phase V: T[c][r] = 2^e sum_p V[p][c] x[p][r] for a tile of up to 16 MT
+// columns of one block (MT column tiles of 16 share every x load) and NT tiles
+// of 16 right-hand sides (group g). K step = 16 rows: lane (i, k) loads rows
+// p0 + 4k .. p0 + 4k + 3 of column i of each column tile; MFMA m uses row
+// p0 + 4k + m for the lane's k. Rows past P and columns past the tile are
+// clamped in bounds with weight zero / discarded.
+template <int FMT, int NT, int MT>
+__device__ void dotm_tile(const DotTask& t, const Desc& D, int R, int g, int lane) {
+    constexpr uint32_t es = elem_bytes<FMT>();
+    const int i = lane & 15, kq = lane >> 4;
+    const int P = t.P;
+    rsrc_t rs[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int c = 16 * mt + i < t.ncols ? 16 * mt + i : t.ncols - 1;
+        rs[mt] = make_rsrc(static_cast<const char*>(t.col0) + (int64_t)c * P * es, (int64_t)P * es);
+    }
+    const double* xb = D.xt + t.xoff * (int64_t)R;
+    int rr[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int r = 16 * (g * NT + u) + i;
+        rr[u] = r < R ? r : R - 1;
+    }
+    // AC independent partial sums per tile pair keep the MFMA chains apart;
+    // they are added in a fixed order at the end
+    constexpr int AC = NT * MT >= 4 ? 1 : 4 / (NT * MT);
+    dbl4_t acc[AC][MT][NT];
+#pragma unroll
+    for (int h = 0; h < AC; ++h)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[h][mt][u] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+    constexpr int KU = NT * MT == 1 ? 4 : NT * MT == 2 ? 2 : 1;
+    for (int p0 = 0; p0 < P; p0 += 16 * KU) {
+        double a[KU][MT][4];
+        double b[KU][4][NT];
+        bool pok[KU];
+#pragma unroll
+        for (int s = 0; s < KU; ++s) {
+            const int p = p0 + 16 * s + 4 * kq;
+            pok[s] = p < P;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                widen4<FMT, double>(bload4<FMT>(rs[mt], (uint32_t)(pok[s] ? p : 0) * es), a[s][mt]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    b[s][m][u] = ldg<double>(xb + (int64_t)(pok[s] ? p + m : 0) * R + rr[u]);
+        }
+#pragma unroll
+        for (int s = 0; s < KU; ++s)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const double am = pok[s] ? a[s][mt][m] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < NT; ++u)
+                        acc[m % AC][mt][u] = mfma16(am, b[s][m][u], acc[m % AC][mt][u]);
+                }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = acc[0][mt][u][r];
+#pragma unroll
+                for (int h = 1; h < AC; ++h) v += acc[h][mt][u][r];
+                const int cm = 16 * mt + 4 * r + kq, rhs = 16 * (g * NT + u) + i;
+                if (cm < t.ncols && rhs < R)
+                    stg<double>(D.tb + (t.toff + cm) * (int64_t)R + rhs, ldexp(v, t.exp));
+            }
+}
+
+// Tiles x right-hand-side groups, four per workgroup (one per wave); the groups
+// of one tile are neighbours, so its columns are read from HBM about once.
+template <int NT>
+__global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, const DotTask* tiles,
+                                                   int64_t ntiles, int R, int ngroups) {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+    if (item >= ntiles * ngroups) return;
+    const int64_t ti = item / ngroups;
+    const int g = (int)(item - ti * ngroups);
+    const DotTask t = ldrec<DotTask>(tiles + ti);
+    const Desc D = descs ? ldrec<Desc>(descs + t.hid) : d;
+    switch (t.fmt) {
+        case HH_FMT_FP64: dotm_tile<HH_FMT_FP64, NT, DOTM_MT>(t, D, R, g, lane); break;
+        case HH_FMT_FP32: dotm_tile<HH_FMT_FP32, NT, DOTM_MT>(t, D, R, g, lane); break;
+        case HH_FMT_FP16: dotm_tile<HH_FMT_FP16, NT, DOTM_MT>(t, D, R, g, lane); break;
+        default: dotm_tile<HH_FMT_BF16, NT, DOTM_MT>(t, D, R, g, lane); break;
+    }
+}
+
+// Phase U for 64 rows of a leaf (four 16-row subtiles q: rows base + 4 i + q)
+// and NT tiles of right-hand sides: lane (i, k) loads rows base + 4i .. + 3 of
+// column c + k, one row per subtile; K step = 4 columns, four steps per pass.
+template <int F, int NT>
+__device__ inline void accm_runs(const Desc& D, int64_t ci, const LeafTask& lt, int rowbase, int R,
+                                 int g, int lane, dbl4_t acc[4][NT]) {
+    constexpr uint32_t es = elem_bytes<F>();
+    const int i = lane & 15, kq = lane >> 4;
+    const int row0 = rowbase + 4 * i;
+    const uint32_t voff = (uint32_t)(row0 < lt.P ? row0 : 0) * es;
+    int rr[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int r = 16 * (g * NT + u) + i;
+        rr[u] = r < R ? r : R - 1;
+    }
+    const int rb = ldc<int32_t>(D.cl_run + 4 * ci + F), re = ldc<int32_t>(D.cl_run + 4 * ci + F + 1);
+    for (int ri = rb; ri < re; ++ri) {
+        const Run rn = ldrec<Run>(D.runs + ri);
+        const double* coef = rn.from_x ? D.xt : D.tb;
+        const int64_t off = lt.poff - rn.pc;
+        const rsrc_t rs = make_rsrc(static_cast<const char*>(rn.base) + off * es,
+                                    ((int64_t)rn.ncols * rn.stride - off) * es);
+        const int n = rn.ncols;
+        constexpr int KS = NT >= 4 ? 2 : 4;           // K steps of 4 columns per pass
+        for (int c = 0; c < n; c += 4 * KS) {
+            double a[KS][4];
+            double b[KS][NT];
+#pragma unroll
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const int cc = c + 4 * s4 + kq;
+                const int ccl = cc < n ? cc : n - 1;
+                widen4<F, double>(bload4<F>(rs, voff + (uint32_t)ccl * (uint32_t)rn.stride * es), a[s4]);
+                if (cc >= n) a[s4][0] = a[s4][1] = a[s4][2] = a[s4][3] = 0.0;
+#pragma unroll
+                for (int u = 0; u < NT; ++u) b[s4][u] = ldg<double>(coef + ((int64_t)rn.toff + ccl) * R + rr[u]);
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < KS; ++s4)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < NT; ++u) acc[q][u] = mfma16(a[s4][q], b[s4][u], acc[q][u]);
+        }
+    }
+}
+
+// One workgroup per (leaf, right-hand-side group); wave w owns rows 64 w ..
+// 64 w + 63 of each 256-row strip of the leaf; writes y in caller order.
+template <int NT>
+__global__ __launch_bounds__(256) void accm_kernel(Desc d, const Desc* descs, const LeafTask* leaves,
+                                                   int R, int ngroups) {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int64_t li = blockIdx.x / ngroups;
+    const int g = (int)(blockIdx.x - li * ngroups);
+    const LeafTask lt = ldrec<LeafTask>(leaves + li);
+    const Desc D = descs ? ldrec<Desc>(descs + lt.hid) : d;
+    const int i = lane & 15, kq = lane >> 4;
+    for (int strip = 0; strip < lt.P; strip += 256) {
+        const int rowbase = strip + 64 * wave;
+        if (rowbase >= lt.P) break;
+        dbl4_t acc[4][NT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[q][u] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+        for (int l = 0; l <= D.L; ++l) {
+            const int64_t ci = cluster_index(D, l, lt.leaf);
+            accm_runs<HH_FMT_FP64, NT>(D, ci, lt, rowbase, R, g, lane, acc);
+            accm_runs<HH_FMT_FP32, NT>(D, ci, lt, rowbase, R, g, lane, acc);
+            accm_runs<HH_FMT_FP16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
+            accm_runs<HH_FMT_BF16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rowbase + 4 * (4 * r + kq) + q;
+                    const int rhs = 16 * (g * NT + u) + i;
+                    if (row >= lt.P || rhs >= R) continue;
+                    const int64_t uidx = ldg<int64_t>(D.pmap + lt.poff + row);
+                    if (uidx < 0) continue;
+                    if (D.io == HH_IO_F64)
+                        stg<double>(static_cast<double*>(D.y) + uidx * R + rhs, acc[q][u][r]);
+                    else
+                        stg<float>(static_cast<float*>(D.y) + uidx * R + rhs, (float)acc[q][u][r]);
+                }
+    }
+}
+
+// RHS tiles of 16 per group: phase V up to four; phase U two (a group of four
+// would need 128 accumulator registers and one wave per SIMD).
+static inline int rhs_tiles_per_group(int R) { return R <= 16 ? 1 : R <= 32 ? 2 : 4; }
+static inline int rhs_tiles_per_group_u(int R) { return R <= 16 ? 1 : 2; }
 
 // ------------------------------------------------------------- launchers
 void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int R, void* stream) {
@@ -644,20 +806,38 @@ void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks, int R,
                 void* stream) {
     if (ntasks <= 0) return;
-    if (R == 1)
+    if (R == 1) {
         hipLaunchKernelGGL(dot1_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
                            d, descs, tasks);
+        return;
+    }
+    // several right-hand sides: tasks are tiles of at most 16 columns
+    const int nt = rhs_tiles_per_group(R);
+    const int ngroups = ((R + 15) / 16 + nt - 1) / nt;
+    const unsigned grid = (unsigned)((ntasks * ngroups + 3) / 4);
+    if (nt == 1)
+        hipLaunchKernelGGL(dotm_kernel<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
+                           tasks, ntasks, R, ngroups);
+    else if (nt == 2)
+        hipLaunchKernelGGL(dotm_kernel<2>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
+                           tasks, ntasks, R, ngroups);
     else
-        hipLaunchKernelGGL(dotn_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
-                           d, descs, tasks, R);
+        hipLaunchKernelGGL(dotm_kernel<4>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
+                           tasks, ntasks, R, ngroups);
 }
 
 void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
                        int R, void* stream) {
     if (nleaves <= 0) return;
-    const unsigned grid = (unsigned)((nleaves + 3) / 4);
-    hipLaunchKernelGGL(accum_kernel<4>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
-                       leaves, nleaves, R);
+    const int nt = rhs_tiles_per_group_u(R);
+    const int ngroups = ((R + 15) / 16 + nt - 1) / nt;
+    const unsigned grid = (unsigned)(nleaves * ngroups);
+    if (nt == 1)
+        hipLaunchKernelGGL(accm_kernel<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
+                           leaves, R, ngroups);
+    else
+        hipLaunchKernelGGL(accm_kernel<2>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
+                           leaves, R, ngroups);
 }
 
 void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,

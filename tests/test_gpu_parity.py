@@ -60,13 +60,31 @@ def test_plain_2d_log_small_config():
     _check_products(g, o, p.points, O.Kernel(p.kernel), p.tol, trans=True)
 
 
-@pytest.mark.parametrize("nrhs", [2, 5, 9])
+@pytest.mark.parametrize("nrhs", [2, 5, 9, 16, 33, 64])
 def test_multiple_rhs(nrhs):
     p = W.cfg_plain_small(seed=5, n=3000)
     g, o = build_pair(p.points, p.kernel, 1e-6, p.eta, -1, 48)
     compare_structure(g, o)
     _check_products(g, o, p.points, O.Kernel(p.kernel), 1e-6, nrhs=nrhs, dense=False)
     _check_products(g, o, p.points, O.Kernel(p.kernel), 1e-6, nrhs=nrhs, trans=True, dense=False)
+
+
+def test_multiple_rhs_equal_columnwise_products_large_leaves():
+    # leaves of about 310 points (two 256-row strips), 3D 1/r, fp64/fp32 storage:
+    # every column of the several-RHS product (MFMA) equals the single-RHS product
+    torch = _torch()
+    from paper_2604_09147_amd import HMatrix
+    rng = np.random.default_rng(9)
+    P = rng.random((20000, 3))
+    g = HMatrix(P, W.INV_R, 1e-6, 1.5, -1, 400, mask=0x3)
+    assert g.stats()["L"] == 2
+    X = torch.from_numpy(rng.standard_normal((20000, 20))).cuda()
+    for trans in (False, True):
+        Y = g.matvec_t(X) if trans else g.matvec(X)
+        for r in (0, 7, 19):
+            y = g.matvec_t(X[:, r].contiguous()) if trans else g.matvec(X[:, r].contiguous())
+            assert float(torch.linalg.norm(Y[:, r] - y) / torch.linalg.norm(y)) <= 1e-13
+    g.free()
 
 
 @pytest.mark.parametrize("kind,d,tol,eta,ell,mask", [
