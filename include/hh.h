@@ -179,9 +179,15 @@ hh_status hh_matvec_t(const hh_handle* h, const void* x, void* y, int64_t nrhs, 
 hh_status hh_matvec_timed(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream,
                           int trans, double* phase_ms);
 
-/* hh_matvec_batch: y_t = H_t^ x_t for `count` independent handles in one pass
- * of the kernels (one launch per phase). Every handle must share io_dtype and
- * the device; x[t], y[t] are DEVICE pointers sized for handle t. */
+/* hh_matvec_batch: y_t = H_t^ x_t (Alg. 4) for `count` independent handles in
+ * one pass of the kernels (one launch per phase over all handles). Every
+ * handle must share io_dtype and the device; x[t], y[t] are DEVICE pointers
+ * sized for handle t (N_t x nrhs, row-major). The task tables of the last
+ * batch (same handles in the same order, same nrhs) stay on the device, so a
+ * repeated call only uploads the x / y descriptors on `stream` and returns
+ * without waiting. Calls that overlap in time (other streams, other threads)
+ * share that descriptor table and the handles' workspaces, and race. Freeing
+ * a handle of the batch drops the tables. */
 hh_status hh_matvec_batch(const hh_handle* const* hs, int count, const void* const* x,
                           void* const* y, int64_t nrhs, void* stream);
 

@@ -6,6 +6,8 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -105,17 +107,40 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     }
 }
 
+// Task tables of the last batch (its handles and RHS count) stay on the
+// device; a call with the same batch only uploads the descriptors (x, y and
+// workspace pointers) on its stream. Freeing a member handle drops the plan.
+struct BatchPlan {
+    std::vector<const hh_handle*> hs;
+    int64_t R = 0;
+    int device = -1;
+    DevMem mem;
+    Desc* d_desc = nullptr;
+    DotTask* d_dot = nullptr;
+    LeafTask* d_leaf = nullptr;
+    UnitTask* d_unit = nullptr;
+    FinishTask* d_fin = nullptr;
+    int64_t ndot = 0, nleaf = 0, nunit = 0, nfin = 0, max_np = 0;
+};
+static std::mutex g_batch_mu;
+static std::unique_ptr<BatchPlan> g_batch;
+
+template <class T>
+static T* upload_to(DevMem& m, const std::vector<T>& v) {
+    T* d = static_cast<T*>(m.alloc(v.size() * sizeof(T) + 16, false));
+    if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
 static void product_batch(const hh_handle* const* hs, int count, const void* const* x,
                           void* const* y, int64_t nrhs, void* stream) {
     if (!hs || !x || !y || count < 1) fail(HH_EINVAL, "batch needs count >= 1 handles, x and y");
     if (nrhs < 1 || nrhs > (1 << 16)) fail(HH_EINVAL, "nrhs must lie in [1, 65536]");
+    if (count > 65535) fail(HH_EINVAL, "at most 65535 handles per batch");
     const int io = hs[0] ? hs[0]->opt.io_dtype : 0;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
     std::vector<Desc> descs(count);
-    std::vector<DotTask> dot;
-    std::vector<LeafTask> leaf;
-    std::vector<UnitTask> unit;
-    std::vector<FinishTask> fin;
-    int64_t max_np = 0;
     for (int t = 0; t < count; ++t) {
         hh_handle* h = const_cast<hh_handle*>(hs[t]);
         if (!h) fail(HH_EINVAL, "a handle in the batch is NULL");
@@ -126,46 +151,69 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
             if (hs[u] == h) fail(HH_EINVAL, "a handle appears twice in the batch (shared workspace)");
         ensure_workspace(h, nrhs);
         descs[t] = make_desc(h, h->fwd, x[t], y[t]);
-        max_np = std::max(max_np, h->np);
-        for (DotTask k : (nrhs == 1 ? h->fwd.dot : h->fwd.dotm)) {
-            k.hid = t;
-            dot.push_back(k);
-        }
-        for (LeafTask k : h->fwd.leaf) {
-            k.hid = t;
-            leaf.push_back(k);
-        }
-        for (UnitTask k : h->fwd.unit) {
-            k.hid = t;
-            unit.push_back(k);
-        }
-        for (FinishTask k : h->fwd.fin) {
-            k.hid = t;
-            fin.push_back(k);
-        }
     }
-    if (count > 65535) fail(HH_EINVAL, "at most 65535 handles per batch");
-    // staging buffers for this call (freed after the stream drains)
-    DevMem tmp;
-    auto up = [&](const void* src, size_t bytes) {
-        void* p = tmp.alloc(bytes + 16, false);
-        if (bytes) HIPCHK(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
-        return p;
-    };
-    Desc* dd = static_cast<Desc*>(up(descs.data(), descs.size() * sizeof(Desc)));
-    DotTask* dt = static_cast<DotTask*>(up(dot.data(), dot.size() * sizeof(DotTask)));
-    LeafTask* dl = static_cast<LeafTask*>(up(leaf.data(), leaf.size() * sizeof(LeafTask)));
-    UnitTask* du = static_cast<UnitTask*>(up(unit.data(), unit.size() * sizeof(UnitTask)));
-    FinishTask* df = static_cast<FinishTask*>(up(fin.data(), fin.size() * sizeof(FinishTask)));
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    BatchPlan* bp = g_batch.get();
+    const bool same = bp && bp->R == nrhs && bp->device == dev && (int)bp->hs.size() == count &&
+                      std::equal(bp->hs.begin(), bp->hs.end(), hs);
+    if (!same) {
+        g_batch.reset();
+        std::unique_ptr<BatchPlan> np(new BatchPlan());
+        np->hs.assign(hs, hs + count);
+        np->R = nrhs;
+        np->device = dev;
+        std::vector<DotTask> dot;
+        std::vector<LeafTask> leaf;
+        std::vector<UnitTask> unit;
+        std::vector<FinishTask> fin;
+        for (int t = 0; t < count; ++t) {
+            const hh_handle* h = hs[t];
+            np->max_np = std::max(np->max_np, h->np);
+            for (DotTask k : (nrhs == 1 ? h->fwd.dot : h->fwd.dotm)) {
+                k.hid = t;
+                dot.push_back(k);
+            }
+            for (LeafTask k : h->fwd.leaf) {
+                k.hid = t;
+                leaf.push_back(k);
+            }
+            for (UnitTask k : h->fwd.unit) {
+                k.hid = t;
+                unit.push_back(k);
+            }
+            for (FinishTask k : h->fwd.fin) {
+                k.hid = t;
+                fin.push_back(k);
+            }
+        }
+        np->d_desc = static_cast<Desc*>(np->mem.alloc(count * sizeof(Desc) + 16, false));
+        np->d_dot = upload_to(np->mem, dot);
+        np->d_leaf = upload_to(np->mem, leaf);
+        np->d_unit = upload_to(np->mem, unit);
+        np->d_fin = upload_to(np->mem, fin);
+        np->ndot = (int64_t)dot.size();
+        np->nleaf = (int64_t)leaf.size();
+        np->nunit = (int64_t)unit.size();
+        np->nfin = (int64_t)fin.size();
+        g_batch = std::move(np);
+        bp = g_batch.get();
+    }
+    HIPCHK(hipMemcpyAsync(bp->d_desc, descs.data(), count * sizeof(Desc), hipMemcpyHostToDevice,
+                          (hipStream_t)stream));
     const int R = (int)nrhs;
-    launch_gather(descs[0], dd, count, max_np, R, stream);
-    launch_dot(descs[0], dd, dt, (int64_t)dot.size(), R, stream);
+    launch_gather(descs[0], bp->d_desc, count, bp->max_np, R, stream);
+    launch_dot(descs[0], bp->d_desc, bp->d_dot, bp->ndot, R, stream);
     if (R == 1)
-        launch_units(descs[0], dd, du, (int64_t)unit.size(), df, (int64_t)fin.size(), stream);
+        launch_units(descs[0], bp->d_desc, bp->d_unit, bp->nunit, bp->d_fin, bp->nfin, stream);
     else
-        launch_accumulate(descs[0], dd, dl, (int64_t)leaf.size(), R, stream);
+        launch_accumulate(descs[0], bp->d_desc, bp->d_leaf, bp->nleaf, R, stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+}
+
+static void drop_batch_plan(const hh_handle* h) {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    if (g_batch && std::find(g_batch->hs.begin(), g_batch->hs.end(), h) != g_batch->hs.end())
+        g_batch.reset();
 }
 
 static double decode(const void* base, int fmt, int64_t i) {
@@ -345,6 +393,7 @@ void hh_free(hh_handle* h) {
     (void)hipGetDevice(&prev);
     if (prev != dev) (void)hipSetDevice(dev);
     (void)hipDeviceSynchronize();
+    drop_batch_plan(h);
     delete h;
     if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
 }
