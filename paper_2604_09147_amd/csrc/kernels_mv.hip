@@ -15,7 +15,8 @@
 //                       leaf's runs are cut into work units of about 1 MB, one
 //                       wave each, writing partial rows that a finishing kernel
 //                       adds in unit order and writes to y in caller order.
-//                       Several RHS: one wave per leaf walks the cluster runs.
+//                       Several RHS: fp64 MFMA on 16-column tiles (phase V) and
+//                       on 64-row leaf slices over the cluster runs (phase U).
 //                       Run records and coefficients are wave-uniform (scalar
 //                       loads); factor data goes through buffer loads. No atomics
 //                       and a fixed order: results are bitwise reproducible.
@@ -270,51 +271,6 @@ __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks
     }
 HH_DOT1_KERNEL(dot1_kernel, 8, 4096, 4)
 
-// Several right-hand sides, RC at a time (columns re-read per chunk of RC).
-template <int FMT, int RC>
-__device__ void dot_rn(const DotTask& t, const double* xt, double* tb, int R, int wave,
-                       int lane) {
-    using acc_t = typename std::conditional<(FMT >= HH_FMT_FP16), float, double>::type;
-    const int P = t.P;
-    for (int r0 = 0; r0 < R; r0 += RC) {
-        const int nr = R - r0 < RC ? R - r0 : RC;
-        for (int c = wave; c < t.ncols; c += 4) {
-            acc_t a[RC];
-#pragma unroll
-            for (int k = 0; k < RC; ++k) a[k] = 0;
-            for (int r = 4 * lane; r < P; r += 256) {
-                acc_t v[4];
-                widen4<FMT, acc_t>(load4<FMT>(t.col0, (int64_t)c * P + r), v);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double* xr = xt + (t.xoff + r + q) * R + r0;
-#pragma unroll
-                    for (int k = 0; k < RC; ++k)
-                        if (k < nr) a[k] = fma(v[q], (acc_t)ldg<double>(xr + k), a[k]);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < RC; ++k) {
-                const double s = ldexp(wave_sum((double)a[k]), t.exp);
-                if (lane == 0 && k < nr) stg<double>(tb + (t.toff + c) * R + r0 + k, s);
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void dotn_kernel(Desc d, const Desc* descs,
-                                                   const DotTask* tasks, int R) {
-    const DotTask t = ldrec<DotTask>(tasks + blockIdx.x);
-    const Desc D = descs ? ldrec<Desc>(descs + t.hid) : d;
-    const int wave = wave_id(), lane = threadIdx.x & 63;
-    switch (t.fmt) {
-        case HH_FMT_FP64: dot_rn<HH_FMT_FP64, 8>(t, D.xt, D.tb, R, wave, lane); break;
-        case HH_FMT_FP32: dot_rn<HH_FMT_FP32, 8>(t, D.xt, D.tb, R, wave, lane); break;
-        case HH_FMT_FP16: dot_rn<HH_FMT_FP16, 8>(t, D.xt, D.tb, R, wave, lane); break;
-        default: dot_rn<HH_FMT_BF16, 8>(t, D.xt, D.tb, R, wave, lane); break;
-    }
-}
-
 // -------------------------------------------------------------- accumulate
 // Apply one run to a lane's 4 rows: acc += 2^e sum_c col_c[rows] coef_c
 // (the power-of-two scale is exact, so applying it to the run's sum rounds as
@@ -387,104 +343,69 @@ __device__ inline void apply_run(const Run& rn, rsrc_t rs, uint32_t voff, const 
     if (c < n) apply_cols<FMT, RC, T, true, SPLIT>(rn, rs, voff, coef, R, r0, nr, c, step, acc);
 }
 
+// One run with software pipelining: the loads of batch b + 1 (UP columns) are
+// issued before batch b is consumed, so a wave always has UP to 2 UP loads in
+// flight; the last columns go through the tiered batches above.
+template <int FMT, int UP>
+__device__ inline void apply_run_pipe(const Run& rn, rsrc_t rs, uint32_t voff, const double* coef,
+                                      double acc[4][1]) {
+    const int n = rn.ncols;
+    const int nb = n / UP;
+    const uint32_t cstep = (uint32_t)rn.stride * elem_bytes<FMT>();
+    if (nb > 0) {
+        Raw4<FMT> cur[UP];
+        double cfc[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            cur[u] = bload4<FMT>(rs, voff + (uint32_t)u * cstep);
+            cfc[u] = ldc<double>(coef + rn.toff + u);
+        }
+        for (int b = 1; b < nb; ++b) {
+            Raw4<FMT> nxt[UP];
+            double cfn[UP];
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                const int c = b * UP + u;
+                nxt[u] = bload4<FMT>(rs, voff + (uint32_t)c * cstep);
+                cfn[u] = ldc<double>(coef + rn.toff + c);
+            }
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                double v[4];
+                widen4<FMT, double>(cur[u], v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q][0] = fma(v[q], cfc[u], acc[q][0]);
+            }
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                cur[u] = nxt[u];
+                cfc[u] = cfn[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            double v[4];
+            widen4<FMT, double>(cur[u], v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][0] = fma(v[q], cfc[u], acc[q][0]);
+        }
+    }
+    int c = nb * UP;
+    if constexpr (UP >= 8) {
+        if (c + UP / 2 - 1 < n) {
+            apply_cols<FMT, 1, UP / 2, false, false>(rn, rs, voff, coef, 1, 0, 1, c, 1, acc);
+            c += UP / 2;
+        }
+    }
+    if (c < n) apply_cols<FMT, 1, 4, true, false>(rn, rs, voff, coef, 1, 0, 1, c, 1, acc);
+}
+
 // Index of the cluster of level l that contains leaf box `leaf`: clusters are
 // numbered level by level, level l starting at sum_{l' < l} 2^(d l').
 __device__ inline int64_t cluster_index(const Desc& D, int l, int64_t leaf) {
     int64_t first = 0;
     for (int i = 0; i < l; ++i) first += (int64_t)1 << (D.d * i);
     return first + (leaf >> (D.d * (D.L - l)));
-}
-
-// The runs of one cluster stored in format F, applied to one leaf's rows.
-template <int F, int RC, bool SPLIT>
-__device__ inline void apply_runs_fmt(const Desc& D, const LeafTask& lt, int64_t ci, int64_t row,
-                                      int R, int r0, int nr, int g, int G, double acc[4][RC]) {
-    constexpr uint32_t es = elem_bytes<F>();
-    const int rb = ldc<int32_t>(D.cl_run + 4 * ci + F), re = ldc<int32_t>(D.cl_run + 4 * ci + F + 1);
-    for (int i = rb; i < re; ++i) {
-        const Run rn = ldrec<Run>(D.runs + i);
-        const double* coef = rn.from_x ? D.xt : D.tb;
-        // the run's columns from the leaf's first row on, as a buffer whose byte
-        // offsets are (column * stride + lane row) * element size
-        const int64_t off = lt.poff - rn.pc;
-        const rsrc_t rs = make_rsrc(static_cast<const char*>(rn.base) + off * es,
-                                    ((int64_t)rn.ncols * rn.stride - off) * es);
-        apply_run<F, RC, SPLIT>(rn, rs, (uint32_t)row * es, coef, R, r0, nr, g, G, acc);
-    }
-}
-
-// Runs of the clusters containing the leaf at levels lmin..L; each cluster
-// lists its runs grouped by storage format.
-template <int RC, bool SPLIT>
-__device__ inline void apply_cluster_runs(const Desc& D, const LeafTask& lt, int64_t row, int R,
-                                          int r0, int nr, int g, int G, double acc[4][RC]) {
-    for (int l = 0; l <= D.L; ++l) {
-        const int64_t ci = cluster_index(D, l, lt.leaf);
-        apply_runs_fmt<HH_FMT_FP64, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
-        apply_runs_fmt<HH_FMT_FP32, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
-        apply_runs_fmt<HH_FMT_FP16, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
-        apply_runs_fmt<HH_FMT_BF16, RC, SPLIT>(D, lt, ci, row, R, r0, nr, g, G, acc);
-    }
-}
-
-// The output rows of one leaf (several right-hand sides, RC per pass): runs
-// of the clusters that contain it, then the write of y.
-template <int RC>
-__device__ void leaf_wave(const Desc& D, const LeafTask& lt, int lane, int R) {
-    const int P = lt.P;
-    int lps = 1;
-    while (lps < 64 && 4 * lps < P) lps <<= 1;  // lanes per column piece
-    const int G = 64 / lps, g = lane / lps, sl = lane % lps;
-    const int strip = 4 * lps;                   // rows per pass
-    for (int jlo = 0; jlo < P; jlo += strip) {
-        for (int r0 = 0; r0 < R; r0 += RC) {
-            const int nr = R - r0 < RC ? R - r0 : RC;
-            const int prow = jlo + 4 * sl;              // this lane's first row
-            const int64_t row = prow < P ? prow : 0;    // clamped: in bounds, never written
-            double acc[4][RC];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int k = 0; k < RC; ++k) acc[q][k] = 0.0;
-            if (G == 1) apply_cluster_runs<RC, false>(D, lt, row, R, r0, nr, 0, 1, acc);
-            else apply_cluster_runs<RC, true>(D, lt, row, R, r0, nr, g, G, acc);
-            // groups covering the same rows, combined in a fixed order
-            for (int off = lps; off < 64; off <<= 1)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int k = 0; k < RC; ++k) acc[q][k] += __shfl_xor(acc[q][k], off, 64);
-            if (g == 0) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (prow + q >= P) continue;
-                    const int64_t u = ldg<int64_t>(D.pmap + lt.poff + prow + q);
-                    if (u < 0) continue;
-#pragma unroll
-                    for (int k = 0; k < RC; ++k) {
-                        if (k >= nr) continue;
-                        if (D.io == HH_IO_F64)
-                            stg<double>(static_cast<double*>(D.y) + u * R + r0 + k, acc[q][k]);
-                        else
-                            stg<float>(static_cast<float*>(D.y) + u * R + r0 + k, (float)acc[q][k]);
-                    }
-                }
-            }
-        }
-    }
-}
-
-// Four leaves per workgroup, one per wave; the waves never synchronise.
-template <int RC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void accum_kernel(Desc d, const Desc* descs,
-                                                    const LeafTask* leaves, int64_t nleaves,
-                                                    int R) {
-    const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int64_t li = (int64_t)blockIdx.x * 4 + wave;
-    if (li >= nleaves) return;
-    const LeafTask lt = ldrec<LeafTask>(leaves + li);
-    const Desc D = descs ? ldrec<Desc>(descs + lt.hid) : d;
-    leaf_wave<RC>(D, lt, lane, R);
 }
 
 // ---------------------------------------------- single-vector work units
@@ -494,7 +415,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
 // kernel adds a leaf's partials in unit order.
 template <int F, bool SPLIT, int UB>
 __device__ inline void unit_runs_fmt(const Desc& D, const UnitTask& ut, int b, int e, int64_t row,
-                                     int g, int G, double acc[4][1]) {
+                                     int g, int G, double acc[4][1], bool pipe) {
     constexpr uint32_t es = elem_bytes<F>();
     if (b >= e) return;
     Run rn = ldrec<Run>(D.uruns + b);
@@ -505,22 +426,25 @@ __device__ inline void unit_runs_fmt(const Desc& D, const UnitTask& ut, int b, i
         const int64_t off = ut.poff - rn.pc;
         const rsrc_t rs = make_rsrc(static_cast<const char*>(rn.base) + off * es,
                                     ((int64_t)rn.ncols * rn.stride - off) * es);
-        apply_run<F, 1, SPLIT, UB>(rn, rs, (uint32_t)row * es, coef, 1, 0, 1, g, G, acc);
+        if (!SPLIT && pipe)
+            apply_run_pipe<F, F == HH_FMT_FP64 ? 4 : 8>(rn, rs, (uint32_t)row * es, coef, acc);
+        else
+            apply_run<F, 1, SPLIT, UB>(rn, rs, (uint32_t)row * es, coef, 1, 0, 1, g, G, acc);
         rn = nx;
     }
 }
 
 template <bool SPLIT, int UB>
 __device__ inline void unit_runs(const Desc& D, const UnitTask& ut, int64_t row, int g, int G,
-                                 double acc[4][1]) {
-    unit_runs_fmt<HH_FMT_FP64, SPLIT, UB>(D, ut, ut.rb, ut.fe[0], row, g, G, acc);
-    unit_runs_fmt<HH_FMT_FP32, SPLIT, UB>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc);
-    unit_runs_fmt<HH_FMT_FP16, SPLIT, UB>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc);
-    unit_runs_fmt<HH_FMT_BF16, SPLIT, UB>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc);
+                                 double acc[4][1], bool pipe) {
+    unit_runs_fmt<HH_FMT_FP64, SPLIT, UB>(D, ut, ut.rb, ut.fe[0], row, g, G, acc, pipe);
+    unit_runs_fmt<HH_FMT_FP32, SPLIT, UB>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc, pipe);
+    unit_runs_fmt<HH_FMT_FP16, SPLIT, UB>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc, pipe);
+    unit_runs_fmt<HH_FMT_BF16, SPLIT, UB>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc, pipe);
 }
 
 // Four units per workgroup, one per wave; the waves never synchronise.
-template <int UB>
+template <int UB, bool PIPE>
 __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int64_t ui = (int64_t)blockIdx.x * 4 + wave;
@@ -536,8 +460,8 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
         const int prow = jlo + 4 * sl;
         const int64_t row = prow < P ? prow : 0;     // clamped: in bounds, never written
         double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
-        if (G == 1) unit_runs<false, UB>(D, ut, row, 0, 1, acc);
-        else unit_runs<true, UB>(D, ut, row, g, G, acc);
+        if (G == 1) unit_runs<false, UB>(D, ut, row, 0, 1, acc, PIPE);
+        else unit_runs<true, UB>(D, ut, row, g, G, acc, PIPE);
         for (int off = lps; off < 64; off <<= 1)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q][0] += __shfl_xor(acc[q][0], off, 64);
@@ -548,12 +472,12 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
     }
 }
 
-#define HH_UNIT_KERNEL(NAME, UB, W)                                                          \
+#define HH_UNIT_KERNEL(NAME, UB, W, PIPE)                                                    \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void NAME(         \
         Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {                    \
-        unit_body<UB>(d, descs, units, nunits);                                                 \
+        unit_body<UB, PIPE>(d, descs, units, nunits);                                           \
     }
-HH_UNIT_KERNEL(unit_kernel, 16, 4)
+HH_UNIT_KERNEL(unit_kernel, 16, 4, true)
 
 // y rows of one leaf: its units' partials in unit order, written in caller
 // order. Lane l owns rows 4l..4l+3 of each 256-row strip.
