@@ -33,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6        # dense fp64 MFMA
 CPU_SAMPLE_N = 16384
 
 
@@ -189,14 +190,29 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
 
-    names = ["gather", "column inner products (dot1_kernel)",
-             "leaf accumulation (unit_kernel + finish_kernel)"]
-    kernels = ["gather_kernel", "dot1_kernel", "accumulation"]
     k = int(np.argmax(ph_a))
-    achieved = sa["phase_bytes"][k] / (ph_a[k] / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(kernels[k], p.n, args.nrhs)}
+    if args.nrhs == 1:
+        names = ["gather", "column inner products (dot1_kernel)",
+                 "leaf accumulation (unit_kernel + finish_kernel)"]
+        kernels = ["gather_kernel", "dot1_kernel", "accumulation"]
+        achieved = sa["phase_bytes"][k] / (ph_a[k] / 1e3) / 1e9
+        roofline = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(kernels[k], p.n, args.nrhs)}
+    else:
+        # several right-hand sides: fp64 MFMA contractions, 2 R flops per stored
+        # entry (phase V: V entries; phase U: U entries and dense entries)
+        names = ["gather", "column inner products (dotm_kernel)", "leaf accumulation (accm_kernel)"]
+        bl = Ha.blocks()
+        lrm = bl["lowrank"].astype(bool)
+        rk = bl["rank"].astype(np.float64)
+        v_entries = float(np.sum((rk * (bl["col_end"] - bl["col_begin"]))[lrm]))
+        u_entries = float(np.sum((rk * (bl["row_end"] - bl["row_begin"]))[lrm]))
+        flops = [0.0, 2.0 * args.nrhs * v_entries, 2.0 * args.nrhs * (u_entries + sa["dense_entries"])]
+        achieved = flops[k] / (ph_a[k] / 1e3) / 1e12
+        roofline = {"bound": "mfma", "kernel": names[k], "achieved": round(achieved, 2),
+                    "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFS, 4),
+                    "traffic": None}
 
     cpu = None
     if worker is not None:
