@@ -50,6 +50,7 @@ constexpr int OVERSAMPLE = 16;
 constexpr int64_t SUM_CHUNK = 65536;
 constexpr int64_t UNIT_BYTES = 1 << 20;   // factor bytes per single-vector work unit
 constexpr int64_t DOT_TASK_ELEMS = 65536;
+constexpr int64_t DOT_X_LDS = 4096;        // rows of x staged in LDS by dot1_kernel
 
 void* DevMem::alloc(size_t bytes, bool zero) {
     void* p = nullptr;
@@ -955,9 +956,11 @@ static void build_tasks(hh_handle* h) {
         for (int pass = 0; pass < 2; ++pass) {
             const int64_t Pl = pass == 0 ? r.PJ : r.PI;
             const char* base = static_cast<const char*>(pass == 0 ? r.v_ptr : r.u_ptr);
-            // about DOT_TASK_ELEMS elements per task, and a column for each wave
+            // about DOT_TASK_ELEMS elements per task and at least one column per
+            // wave; columns too long for the LDS stage of x go four to a wave
+            const int64_t cmin = Pl > DOT_X_LDS ? 16 : 4;
             const int64_t cpt = std::min<int64_t>(
-                r.rank, std::max<int64_t>(4, DOT_TASK_ELEMS / std::max<int64_t>(Pl, 1)));
+                r.rank, std::max<int64_t>(cmin, DOT_TASK_ELEMS / std::max<int64_t>(Pl, 1)));
             for (int64_t c0 = 0; c0 < r.rank; c0 += cpt) {
                 DotTask t{};
                 t.col0 = base + (size_t)(c0 * Pl) * es;

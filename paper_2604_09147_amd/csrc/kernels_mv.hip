@@ -238,7 +238,10 @@ __device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs,
     constexpr int NF = FMT == HH_FMT_FP64 ? NU / 2 : NU;   // loads of 16 bytes per lane
     const int nb = (t.P + 255) / 256;
     constexpr int R2 = NF < 2 ? NF : 2, R4 = NF < 4 ? NF : 4, R8 = NF < 8 ? NF : 8;
-    if (nb <= 1) dot_r1<FMT, 1, NU>(t, xg, xs, lds, tb, wave, lane);
+    // x not staged in LDS (long columns): four columns per pass share each x
+    // load (two for fp64)
+    if (!lds && nb > 2) dot_r1<FMT, R2, NU>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 1) dot_r1<FMT, 1, NU>(t, xg, xs, lds, tb, wave, lane);
     else if (nb <= 2) dot_r1<FMT, R2, NU>(t, xg, xs, lds, tb, wave, lane);
     else if (nb <= 4) dot_r1<FMT, R4, NU>(t, xg, xs, lds, tb, wave, lane);
     else dot_r1<FMT, R8, NU>(t, xg, xs, lds, tb, wave, lane);
