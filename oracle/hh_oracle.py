@@ -782,3 +782,86 @@ def structure_arrays(hm: HMatrix) -> dict:
         "eU": np.array([s.eU for s in bl], dtype=np.int32),
         "eV": np.array([s.eV for s in bl], dtype=np.int32),
     }
+
+
+# --------------------------------------------------------------------------
+# Choice of the switching level (Sec. 3.3: eq:S1, eq:S2, Alg. 2).
+#
+# H_s and H_h(ell) share the coarse interaction lists of levels 1..ell and the
+# dense leaf diagonal; they differ in S1(ell) (what H_s stores below ell: its
+# interaction lists of levels ell+1..L and its leaf neighbours N_s(L)) and
+# S2(ell) (what H_h stores instead: the compressed neighbours N_s(ell) and the
+# weak sibling lists of levels ell+1..L). Storage is counted in 64-bit words
+# weighted by each block's storage bits, so the same sums serve the uniform
+# scheme (every block fp64) and the mixed one.
+# --------------------------------------------------------------------------
+def block_words(sb: StoredBlock) -> float:
+    """64-bit words of one stored block: k (m + n) bits / 64 low rank, m n dense."""
+    b = sb.blk
+    if sb.lowrank:
+        return sb.rank * (b.m + b.n) * BITS[sb.fmt] / 64.0
+    return float(b.m * b.n)
+
+
+def s1_by_level(hs: HMatrix) -> np.ndarray:
+    """S1(ell) for ell = 0..L (eq:S1), read from the H_s representation
+    (switching level L): interaction lists of levels ell+1..L plus the leaf
+    neighbours, stored densely or, in the mixed scheme, as low rank where
+    that is cheaper."""
+    L = hs.tree.L
+    if hs.ell != L:
+        raise ValueError("S1 is read from the H_s representation (switching level L)")
+    far = np.zeros(L + 2)
+    near_leaf = 0.0
+    for sb in hs.blocks:
+        if sb.blk.kind == T_FAR:
+            far[sb.blk.level] += block_words(sb)
+        elif sb.blk.kind == T_DENSE_NEAR:
+            near_leaf += block_words(sb)
+    # S1(ell) = sum over levels l > ell of far[l], plus the leaf neighbours
+    return np.array([far[ell + 1:].sum() + near_leaf for ell in range(L + 1)])
+
+
+def s2_of(hh: HMatrix) -> float:
+    """S2(ell) (eq:S2) of an H_h representation with switching level ell < L:
+    its compressed neighbours N_s(ell) plus its sibling lists IL_w of levels
+    ell+1..L."""
+    if hh.ell >= hh.tree.L:
+        raise ValueError("S2 is defined here for ell < L; S2(L) = S1(L)")
+    return float(sum(block_words(sb) for sb in hh.blocks if sb.blk.kind in (T_NEAR, T_WEAK)))
+
+
+def switch_level_search(L: int, s1: np.ndarray, s2_fn) -> tuple:
+    """Alg. 2: start at ell = L with gain S1(L) - S2(L) = 0 and lower ell while
+    the gain S1(ell - 1) - S2(ell - 1) strictly grows; S2 is asked for only at
+    the levels the walk reaches. Returns (ell*, {ell: gain})."""
+    ell, s = L, 0.0
+    gains = {L: 0.0}
+    while ell > 0:
+        s_new = float(s1[ell - 1]) - float(s2_fn(ell - 1))
+        gains[ell - 1] = s_new
+        if s_new <= s:
+            break
+        s, ell = s_new, ell - 1
+    return ell, gains
+
+
+def optimal_switch_level(points: np.ndarray, kern: Kernel, eps: float, eta: float,
+                         leaf_size: int, mask: int = 0xF, uniform: bool = False,
+                         seed: int = 0) -> dict:
+    """Build H_s, read S1 for every level, then walk Alg. 2 building H_h(ell)
+    for each level it reaches."""
+    hs = build(points, kern, eps, eta, build_tree(points, leaf_size).L, leaf_size,
+               mask=mask, uniform=uniform, seed=seed)
+    L = hs.tree.L
+    s1 = s1_by_level(hs)
+    s2 = {L: float(s1[L])}
+
+    def s2_fn(ell):
+        hh = build(points, kern, eps, eta, ell, leaf_size, mask=mask, uniform=uniform, seed=seed)
+        s2[ell] = s2_of(hh)
+        return s2[ell]
+
+    ell, gains = switch_level_search(L, s1, s2_fn)
+    return {"ell": ell, "L": L, "s1": s1, "s2": s2, "gains": gains,
+            "storage_hs": storage(hs)["total"]}
