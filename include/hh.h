@@ -158,6 +158,31 @@ hh_status hh_build(const double* points, int64_t n, int d, const hh_kernel* k,
  * has ell == L (its dense neighbours carry no factors). */
 hh_status hh_derive(const hh_handle* src, const hh_options* opt, hh_handle** out);
 
+/* hh_switch_level_search: the switching level of Sec. 3.3 (Alg. 2) that the
+ * walk from ell = L downward finds for the storage gain S1(ell) - S2(ell) of
+ * H_h over H_s (eq:S1, eq:S2). Builds H_s (switching level L) with hh_build's
+ * arguments and reads S1(ell) for every ell from it (interaction lists of
+ * levels ell+1..L plus the leaf neighbours); then, for ell = L-1, L-2, ...,
+ * builds H_h(ell) and reads S2(ell) (compressed neighbours N_s(ell) plus the
+ * sibling lists of levels ell+1..L), stopping at the first level whose gain
+ * does not exceed the previous one (a tie stops the walk). Storage is counted
+ * in 64-bit words weighted by each block's storage bits (k (m + n) bits / 64
+ * for factors, m n for dense blocks), so opt->uniform_fp64 = 1 gives the
+ * paper's uniform-precision choice and the adaptive rule the mixed-precision
+ * one. Every handle is freed before returning; each build needs the device
+ * memory hh_build needs, and the call takes the time of all its builds.
+ *   points, n, d, k, tol, eta, leaf_size, opt   as for hh_build.
+ *   level_out   HOST, receives ell* (-1 on failure).
+ *   s1, s2      HOST arrays of cap doubles, or NULL. On success
+ *               s1[ell] = S1(ell) for ell = 0..L; s2[ell] = S2(ell) for the
+ *               levels the walk built, s2[L] = S1(L), NaN elsewhere.
+ *   cap         entries of s1 / s2; HH_EINVAL if either is non-NULL and
+ *               cap < L + 1 (hh_plan_info gives L).
+ * Errors of a build are returned as hh_build returns them. */
+hh_status hh_switch_level_search(const double* points, int64_t n, int d, const hh_kernel* k,
+                                 double tol, double eta, int leaf_size, const hh_options* opt,
+                                 int32_t* level_out, double* s1, double* s2, int32_t cap);
+
 /* -------------------------------------------------------------- products */
 
 /* hh_matvec: y = H^ x (Alg. 4): for every low-rank block y_I += U_b (V_b^T x_J),

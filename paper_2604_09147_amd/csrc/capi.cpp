@@ -216,6 +216,56 @@ static void drop_batch_plan(const hh_handle* h) {
         g_batch.reset();
 }
 
+// 64-bit words one stored block occupies: k (m + n) bits / 64 as factors,
+// m n dense (the storage measure of eq:S1 / eq:S2, weighted by format bits).
+static double block_words(const BlockRec& r) {
+    const double m = (double)(r.b.ie - r.b.ib), n = (double)(r.b.je - r.b.jb);
+    if (!r.lowrank) return m * n;
+    const double bits = r.fmt == HH_FMT_FP64 ? 64.0 : r.fmt == HH_FMT_FP32 ? 32.0 : 16.0;
+    return (double)r.rank * (m + n) * bits / 64.0;
+}
+
+// Sec. 3.3, Alg. 2. H_s (switching level L) gives S1(ell) for every ell: its
+// interaction lists of levels ell+1..L plus its leaf neighbours. Each H_h(ell)
+// the walk reaches gives S2(ell): its compressed neighbours N_s(ell) plus its
+// sibling lists of levels ell+1..L. The walk lowers ell from L while the gain
+// S1 - S2 strictly grows.
+static int switch_level_search(const double* points, int64_t n, int d, const hh_kernel* k,
+                               double tol, double eta, int leaf_size, const hh_options* opt,
+                               double* s1, double* s2, int cap) {
+    const int L = make_plan(points, n, d, eta, -1, leaf_size).L;
+    if ((s1 || s2) && cap < L + 1) fail(HH_EINVAL, "s1 / s2 need L + 1 entries");
+    std::unique_ptr<hh_handle, void (*)(hh_handle*)> hs(
+        build_handle(points, n, d, k, tol, eta, L, leaf_size, opt), hh_free);
+    std::vector<double> far(L + 2, 0.0), S1(L + 1), S2(L + 1, std::nan(""));
+    double near_leaf = 0.0;
+    for (const auto& r : hs->blocks) {
+        if (r.b.kind == HH_BLK_FAR) far[r.b.level] += block_words(r);
+        else if (r.b.kind == HH_BLK_DENSE_NEAR) near_leaf += block_words(r);
+    }
+    hs.reset();
+    for (int ell = L; ell >= 0; --ell) S1[ell] = (ell == L ? 0.0 : S1[ell + 1] + far[ell + 1]);
+    for (int ell = 0; ell <= L; ++ell) S1[ell] += near_leaf;
+    S2[L] = S1[L];
+    int ell = L;
+    double gain = 0.0;
+    while (ell > 0) {
+        std::unique_ptr<hh_handle, void (*)(hh_handle*)> hb(
+            build_handle(points, n, d, k, tol, eta, ell - 1, leaf_size, opt), hh_free);
+        double w = 0.0;
+        for (const auto& r : hb->blocks)
+            if (r.b.kind == HH_BLK_NEAR || r.b.kind == HH_BLK_WEAK) w += block_words(r);
+        S2[ell - 1] = w;
+        const double g = S1[ell - 1] - w;
+        if (g <= gain) break;
+        gain = g;
+        --ell;
+    }
+    if (s1) std::copy(S1.begin(), S1.end(), s1);
+    if (s2) std::copy(S2.begin(), S2.end(), s2);
+    return ell;
+}
+
 static double decode(const void* base, int fmt, int64_t i) {
     switch (fmt) {
         case HH_FMT_FP64: return static_cast<const double*>(base)[i];
@@ -266,6 +316,17 @@ hh_status hh_derive(const hh_handle* src, const hh_options* opt, hh_handle** out
     if (!out || !src) fail(HH_EINVAL, "src and out must not be NULL");
     check_device(src);
     *out = derive_handle(src, opt);
+    GUARD_END
+}
+
+hh_status hh_switch_level_search(const double* points, int64_t n, int d, const hh_kernel* k,
+                                 double tol, double eta, int leaf_size, const hh_options* opt,
+                                 int32_t* level_out, double* s1, double* s2, int32_t cap) {
+    GUARD_BEGIN
+    if (!level_out) fail(HH_EINVAL, "level_out is NULL");
+    if (!points) fail(HH_EINVAL, "points is NULL");
+    *level_out = -1;
+    *level_out = switch_level_search(points, n, d, k, tol, eta, leaf_size, opt, s1, s2, cap);
     GUARD_END
 }
 

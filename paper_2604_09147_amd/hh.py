@@ -21,8 +21,8 @@ IO_F64, IO_F32 = 0, 1
 BLK_FAR, BLK_NEAR, BLK_WEAK, BLK_DIAG, BLK_DENSE_NEAR = range(5)
 
 # Exported functions, in the order include/hh.h declares them.
-EXPORTS = ["hh_build", "hh_derive", "hh_matvec", "hh_matvec_t", "hh_matvec_timed",
-           "hh_matvec_batch", "hh_reserve",
+EXPORTS = ["hh_build", "hh_derive", "hh_switch_level_search", "hh_matvec", "hh_matvec_t",
+           "hh_matvec_timed", "hh_matvec_batch", "hh_reserve",
            "hh_get_stats", "hh_block_count", "hh_get_block", "hh_get_block_factors",
            "hh_get_perm", "hh_io_dtype", "hh_size", "hh_free", "hh_plan_create", "hh_plan_info",
            "hh_plan_blocks", "hh_plan_perm", "hh_plan_free", "hh_quantize", "hh_last_error"]
@@ -93,6 +93,9 @@ def lib() -> C.CDLL:
         "hh_build": ([_DP, C.c_int64, C.c_int, C.POINTER(Kernel), C.c_double, C.c_double, C.c_int,
                       C.c_int, C.POINTER(Options), C.POINTER(_P)], C.c_int),
         "hh_derive": ([_P, C.POINTER(Options), C.POINTER(_P)], C.c_int),
+        "hh_switch_level_search": ([_DP, C.c_int64, C.c_int, C.POINTER(Kernel), C.c_double,
+                                    C.c_double, C.c_int, C.POINTER(Options), _I32P, _DP, _DP,
+                                    C.c_int32], C.c_int),
         "hh_matvec": ([_P, _P, _P, C.c_int64, _P], C.c_int),
         "hh_matvec_t": ([_P, _P, _P, C.c_int64, _P], C.c_int),
         "hh_matvec_timed": ([_P, _P, _P, C.c_int64, _P, C.c_int, _DP], C.c_int),
@@ -176,6 +179,38 @@ def quantize(values, fmt: int, e: int = 0) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ handles
+def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, seed):
+    """hh_kernel and hh_options structs (and the normals array they point to)."""
+    nrm = None
+    k = Kernel(int(kernel), float(scale), float(h), None)
+    if normals is not None:
+        nrm = np.ascontiguousarray(normals, dtype=np.float64)
+        k.normals = _dptr(nrm)
+    o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io_dtype == "f32" else IO_F64,
+                int(seed))
+    return k, o, nrm
+
+
+def switch_level_search(points, kernel: int, tol: float, eta: float, leaf_size: int,
+                        scale: float = 1.0, h: float = 1.0, normals=None, mask: int = 0xF,
+                        uniform_fp64: bool = False, seed: int = 0) -> dict:
+    """Switching level chosen by the walk of Alg. 2 over the storage gains
+    S1(ell) - S2(ell) (hh_switch_level_search): {"ell", "L", "s1", "s2"}, with
+    s2 NaN at the levels the walk did not build."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, d = pts.shape
+    k, o, _nrm = _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, "f64", seed)
+    L = plan(pts, eta, -1, leaf_size)["L"]
+    s1 = np.empty(L + 1)
+    s2 = np.empty(L + 1)
+    ell = C.c_int32()
+    _torch_context()
+    _check(lib().hh_switch_level_search(_dptr(pts), n, d, C.byref(k), float(tol), float(eta),
+                                        int(leaf_size), C.byref(o), C.byref(ell), _dptr(s1),
+                                        _dptr(s2), L + 1))
+    return {"ell": ell.value, "L": L, "s1": s1, "s2": s2}
+
+
 def _torch_context() -> None:
     """Let torch create its device context before the library's first HIP call
     (both then share the one initialised runtime)."""
@@ -205,13 +240,8 @@ class HMatrix:
         else:
             pts = np.ascontiguousarray(points, dtype=np.float64)
             n, d = pts.shape
-            self._normals = None
-            k = Kernel(int(kernel), float(scale), float(h), None)
-            if normals is not None:
-                self._normals = np.ascontiguousarray(normals, dtype=np.float64)
-                k.normals = _dptr(self._normals)
-            o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io_dtype == "f32" else IO_F64,
-                        int(seed))
+            k, o, self._normals = _kernel_options(kernel, scale, h, normals, mask, uniform_fp64,
+                                                  io_dtype, seed)
             _torch_context()
             hp = _P()
             _check(lib().hh_build(_dptr(pts), n, d, C.byref(k), float(tol), float(eta),

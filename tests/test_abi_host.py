@@ -120,3 +120,24 @@ def test_invalid_arguments_rejected_on_host():
         assert lib.hh_last_error()
     assert lib.hh_matvec(None, None, None, 1, None) == hh.HH_EINVAL
     lib.hh_free(None)
+
+
+def test_switch_level_search_rejects_bad_arguments_on_host():
+    # argument errors come back before any build touches the device
+    hh = _lib_or_skip()
+    lib = hh.lib()
+    P = np.ascontiguousarray(np.random.default_rng(1).random((2048, 2)))   # L = 3 at leaf 32
+    pp = P.ctypes.data_as(C.POINTER(C.c_double))
+    k = hh.Kernel(hh.INV_R, 1.0, 1.0, None)
+    lvl = C.c_int32(7)
+    s = np.zeros(8)
+    sp = s.ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.hh_switch_level_search(pp, 2048, 2, C.byref(k), 1e-6, 1.0, 32, None, None, sp, sp,
+                                      8) == hh.HH_EINVAL
+    # s1 / s2 need L + 1 = 4 entries
+    assert lib.hh_switch_level_search(pp, 2048, 2, C.byref(k), 1e-6, 1.0, 32, None, C.byref(lvl),
+                                      sp, None, 3) == hh.HH_EINVAL
+    assert lvl.value == -1 and "L + 1" in lib.hh_last_error().decode()
+    for tol, eta, leaf in ((0.0, 1.0, 32), (1e-6, 0.0, 32), (1e-6, 1.0, 0)):
+        assert lib.hh_switch_level_search(pp, 2048, 2, C.byref(k), tol, eta, leaf, None,
+                                          C.byref(lvl), None, None, 0) == hh.HH_EINVAL
