@@ -90,6 +90,37 @@ def cpu_worker(out_path: str, budget_s: float) -> None:
                    "ell": hm.ell}, f)
 
 
+def switch_level_bench(n: int) -> int:
+    """Time the switching-level search (Alg. 2: H_s, then H_h(ell) builds while
+    the storage gain grows) on the 3D Laplace recipe at N = n, in the uniform
+    fp64 and the mixed scheme; prints one JSON line of its own."""
+    import torch
+
+    import workloads as W
+    from paper_2604_09147_amd import switch_level_search
+
+    torch.cuda.set_device(0)
+    torch.zeros(1, device="cuda")
+    p = W.cfg_3d_laplace(n=n)
+    out = {"metric": "switch_level_search_seconds", "unit": "s", "higher_is_better": False,
+           "data": "synthetic",
+           "config": {"workload": f"3D Laplace 1/(4 pi r), N={p.n} uniform in [0,1]^3, "
+                                  f"leaf {p.leaf_size}, eta {p.eta}, tol {p.tol}"}}
+    for name, uniform in (("uniform_fp64", True), ("adaptive", False)):
+        print(f"bench: switching-level search, {name}, N={p.n}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = switch_level_search(p.points, p.kernel, p.tol, p.eta, p.leaf_size, scale=p.scale,
+                                uniform_fp64=uniform)
+        el = time.perf_counter() - t0
+        walked = [l for l in range(r["L"] + 1) if not math.isnan(r["s2"][l])]
+        out[name] = {"seconds": round(el, 2), "ell": r["ell"], "L": r["L"], "builds": len(walked),
+                     "gain_words": {str(l): float(r["s1"][l] - r["s2"][l]) for l in walked},
+                     "s1_words": [float(v) for v in r["s1"]]}
+        print(f"bench: {name}: ell* = {r['ell']} in {el:.1f} s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +133,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--switch-level", action="store_true",
+                    help="time the switching-level search (Alg. 2) at --n instead")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -111,6 +144,8 @@ def main() -> int:
         print("bench.py measures one GPU: the H_h product here runs on a single MI355X "
               "(--gpus 1); multi-GPU runs are not part of this benchmark.", file=sys.stderr)
         return 2
+    if args.switch_level:
+        return switch_level_bench(args.n)
 
     # CPU baseline in a child process, overlapped with the GPU build
     worker = None
