@@ -258,13 +258,13 @@ class HMatrix:
         dt = torch.float32 if self.io_dtype == "f32" else torch.float64
         if x.dtype != dt:
             raise TypeError(f"x must be {dt} for this handle")
-        if x.shape[0] != self.n or x.dim() not in (1, 2):
+        if x.dim() not in (1, 2) or x.shape[0] != self.n:
             raise ValueError(f"x must have shape ({self.n},) or ({self.n}, nrhs)")
         xc = x.contiguous()
         nrhs = 1 if x.dim() == 1 else x.shape[1]
         y = torch.empty_like(xc) if out is None else out
-        if y.shape != xc.shape or y.dtype != dt or not y.is_contiguous():
-            raise ValueError("out must be a contiguous tensor shaped like x")
+        if not y.is_cuda or y.shape != xc.shape or y.dtype != dt or not y.is_contiguous():
+            raise ValueError("out must be a contiguous device tensor shaped like x")
         return xc, y, nrhs
 
     def matvec(self, x, out=None, stream=None):
@@ -356,14 +356,21 @@ class HMatrix:
 
 
 def matvec_batch(mats, xs, ys=None, stream=None):
-    """y_t = H_t^ x_t for every handle in one pass of the kernels."""
-    import torch
+    """y_t = H_t^ x_t for every handle in one pass of the kernels. Every x_t
+    (and y_t, if given) is checked against its handle as in HMatrix.matvec,
+    and all must carry the same number of right-hand sides."""
     count = len(mats)
-    if ys is None:
-        ys = [torch.empty_like(x) for x in xs]
-    nrhs = 1 if xs[0].dim() == 1 else xs[0].shape[1]
+    if count == 0 or len(xs) != count or (ys is not None and len(ys) != count):
+        raise ValueError("matvec_batch needs one x (and one y, if given) per handle")
+    prepped = [m._prep(x, None if ys is None else y)
+               for m, x, y in zip(mats, xs, ys if ys is not None else [None] * count)]
+    nrhs = prepped[0][2]
+    if any(p[2] != nrhs or p[0].dim() != prepped[0][0].dim() for p in prepped):
+        raise ValueError("every x of a batch must have the same number of right-hand sides")
+    xcs = [p[0] for p in prepped]        # contiguous inputs, alive for the call
+    outs = [p[1] for p in prepped]
     hs = (_P * count)(*[m._h for m in mats])
-    xp = (_P * count)(*[C.c_void_p(x.data_ptr()) for x in xs])
-    yp = (_P * count)(*[C.c_void_p(y.data_ptr()) for y in ys])
+    xp = (_P * count)(*[C.c_void_p(x.data_ptr()) for x in xcs])
+    yp = (_P * count)(*[C.c_void_p(y.data_ptr()) for y in outs])
     _check(lib().hh_matvec_batch(hs, count, xp, yp, nrhs, _stream_ptr(stream)))
-    return ys
+    return outs

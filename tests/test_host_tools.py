@@ -1,7 +1,8 @@
 """CPU tests of the host-side tooling around the product: the benchmark's
-one-GPU refusal, its lookup of the committed HBM counter summary, and the loud
+one-GPU refusal, its lookup of the committed HBM counter summary, the loud
 failure of the binding when the library has not been built (there is no CPU
-fallback path)."""
+fallback path), and the binding's argument checks, which run before any
+device pointer reaches the library."""
 import hashlib
 import json
 import os
@@ -69,3 +70,28 @@ def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(hh, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         hh.lib()
+
+
+def _fake_handle(n, io="f64"):
+    # an HMatrix shell with no native handle: enough for the argument checks,
+    # which run before any library call
+    from paper_2604_09147_amd.hh import HMatrix
+    m = HMatrix.__new__(HMatrix)
+    m._h = None
+    m.n = n
+    m.io_dtype = io
+    return m
+
+
+def test_product_arguments_checked_before_the_library():
+    import torch
+    from paper_2604_09147_amd import matvec_batch
+    a, b = _fake_handle(10), _fake_handle(12)
+    with pytest.raises(ValueError, match="device tensor"):
+        a.matvec(torch.zeros(10, dtype=torch.float64))
+    with pytest.raises(ValueError, match="one x"):
+        matvec_batch([a, b], [torch.zeros(10, dtype=torch.float64)])
+    with pytest.raises(ValueError, match="one x"):
+        matvec_batch([], [])
+    with pytest.raises(ValueError, match="device tensor"):
+        matvec_batch([a, b], [torch.zeros(10, dtype=torch.float64), torch.zeros(12, dtype=torch.float64)])
