@@ -48,6 +48,12 @@ R8 rounding: round-to-nearest-even straight from float64 to the storage format;
    each fp16 factor is first scaled by 2^-e with e = floor(log2 max|F|) - 14, each
    bf16 factor by 2^-e with e = floor(log2 max|F|); fp32 / fp64 are unscaled.
 R9 singular kernels have H_ii = 0 and entries of coincident distinct points 0.
+R10 q43 (8 bits: sign, 4 exponent bits, 3 fraction bits, normal exponents
+   -6..7, largest value 240) has unit roundoff 2^-4, the value its 3 fraction
+   bits give (the table's printed 2.5e-1 does not match them); rounding is
+   ties-to-even with gradual underflow (spacing 2^-9 below 2^-6), and each q43
+   factor is scaled by 2^-e with e = floor(log2 max|F|) - 6, so its largest
+   entry lands in [64, 128) and nothing overflows.
 """
 from __future__ import annotations
 
@@ -57,12 +63,14 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from workloads import (LOG, INV_R, INV_R2, GAUSS, MATERN, DOUBLE_LAYER,
-                       FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16)
+                       FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16, FMT_Q43)
 
 # Unit roundoffs of the storage formats (Table tab:precisions, exact powers of two).
 UNIT = {FMT_FP64: 2.0 ** -53, FMT_FP32: 2.0 ** -24, FMT_FP16: 2.0 ** -11,
-        FMT_BF16: 2.0 ** -8}
-BITS = {FMT_FP64: 64, FMT_FP32: 32, FMT_FP16: 16, FMT_BF16: 16}
+        FMT_BF16: 2.0 ** -8, FMT_Q43: 2.0 ** -4}
+BITS = {FMT_FP64: 64, FMT_FP32: 32, FMT_FP16: 16, FMT_BF16: 16, FMT_Q43: 8}
+# q43 (R10): 4 significant bits, normal exponents -6..7, largest value 240.
+Q43_EMIN, Q43_EMAX, Q43_SIG = -6, 7, 4
 
 # Block types.
 T_FAR, T_NEAR, T_WEAK, T_DIAG, T_DENSE_NEAR = 0, 1, 2, 3, 4
@@ -511,6 +519,41 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
     return out
 
 
+def round_q43(x: np.ndarray) -> np.ndarray:
+    """Nearest q43 value (ties to even) of each float64, returned as float64;
+    magnitudes from 248 (halfway between 240 and the next binade) up become inf."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = x != 0.0
+    ax = np.abs(x[nz])
+    _, q = np.frexp(ax)                          # ax = f 2^q, f in [0.5, 1)
+    e = np.maximum(q - 1, Q43_EMIN)              # exponent of the leading bit
+    ulp = np.ldexp(1.0, e - (Q43_SIG - 1))       # 2^-9 below the normal range
+    r = np.rint(ax / ulp) * ulp
+    out[nz] = np.sign(x[nz]) * r
+    top = (2.0 - 2.0 ** -(Q43_SIG - 1)) * 2.0 ** Q43_EMAX
+    out[np.abs(out) > top] = np.sign(out[np.abs(out) > top]) * np.inf
+    return out
+
+
+def q43_bits(v: np.ndarray) -> np.ndarray:
+    """uint8 codes (sign, biased exponent, fraction) of q43 values held exactly
+    in float64; exponent field 0 holds the subnormals."""
+    v = np.asarray(v, dtype=np.float64)
+    out = np.zeros(v.shape, dtype=np.uint8)
+    a = np.abs(v)
+    sign = (np.signbit(v)).astype(np.uint8) << 7
+    _, q = np.frexp(np.where(a > 0, a, 1.0))
+    e = q - 1
+    normal = a >= 2.0 ** Q43_EMIN
+    frac_n = np.rint((np.ldexp(a, -e) - 1.0) * 8.0).astype(np.int64)
+    frac_s = np.rint(np.ldexp(a, 9)).astype(np.int64)
+    field = np.where(normal, e + 7, 0)
+    frac = np.where(normal, frac_n, frac_s)
+    out[...] = sign | (field.astype(np.uint8) << 3) | frac.astype(np.uint8)
+    return out
+
+
 def bf16_bits(v: np.ndarray) -> np.ndarray:
     """uint16 bit patterns of bfloat16 values held exactly in float64."""
     return (np.asarray(v, dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16)
@@ -524,7 +567,11 @@ def scale_exponent(F: np.ndarray, fmt: int) -> int:
         return 0
     _, q = math.frexp(mx)
     top = q - 1                              # floor(log2 mx)
-    return top - 14 if fmt == FMT_FP16 else top
+    if fmt == FMT_FP16:
+        return top - 14
+    if fmt == FMT_Q43:
+        return top - 6
+    return top
 
 
 def round_to(G: np.ndarray, fmt: int) -> np.ndarray:
@@ -538,6 +585,8 @@ def round_to(G: np.ndarray, fmt: int) -> np.ndarray:
     if fmt == FMT_FP16:
         with np.errstate(over="ignore"):
             return G.astype(np.float16).astype(np.float64)
+    if fmt == FMT_Q43:
+        return round_q43(G)
     return round_bf16(G)
 
 
@@ -551,9 +600,16 @@ def quantize(F: np.ndarray, fmt: int) -> tuple:
         raw = G.astype(np.float32)
     elif fmt == FMT_FP16:
         raw = G.astype(np.float16)
+    elif fmt == FMT_Q43:
+        raw = q43_bits(round_q43(G))
     else:
         raw = bf16_bits(round_bf16(G))
-    stored = round_bf16(G) if fmt == FMT_BF16 else raw.astype(np.float64)
+    if fmt == FMT_BF16:
+        stored = round_bf16(G)
+    elif fmt == FMT_Q43:
+        stored = round_q43(G)
+    else:
+        stored = raw.astype(np.float64)
     return stored, raw, e
 
 
@@ -564,7 +620,7 @@ def choose_format(nb2: float, total2: float, level: int, d: int, eps: float,
                   mask: int) -> int:
     """Largest available unit roundoff u with u <= eps / (2^(dl/2) xi_b)."""
     rhs = (eps * eps) * total2
-    for fmt in (FMT_BF16, FMT_FP16, FMT_FP32):
+    for fmt in (FMT_Q43, FMT_BF16, FMT_FP16, FMT_FP32):
         if mask & (1 << fmt):
             u = UNIT[fmt]
             if ((u * u) * (2.0 ** (d * level))) * nb2 <= rhs:

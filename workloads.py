@@ -26,6 +26,10 @@ KERNEL_NAMES = {LOG: "log", INV_R: "inv_r", INV_R2: "inv_r2", GAUSS: "gauss",
 # Storage-format bits of the precision mask (same as the C header).
 FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16 = 0, 1, 2, 3
 MASK_ALL = 0xF
+# 8-bit quarter precision q43 (1 sign, 4 exponent, 3 fraction bits) of the
+# paper's format table: mask bit 4 of the oracle; not a storage format of the
+# C header.
+FMT_Q43 = 4
 
 
 def uniform_cube(n: int, d: int, rng, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
