@@ -54,6 +54,13 @@ R10 q43 (8 bits: sign, 4 exponent bits, 3 fraction bits, normal exponents
    ties-to-even with gradual underflow (spacing 2^-9 below 2^-6), and each q43
    factor is scaled by 2^-e with e = floor(log2 max|F|) - 6, so its largest
    entry lands in [64, 128) and nothing overflows.
+R11 continuum storage (the accessor remark of Sec. 4.3, which names no format):
+   each entry keeps its own 8-bit exponent (normal exponents -126..127, gradual
+   underflow) and t fraction bits, ties to even, so u = 2^-(t+1) and an entry
+   takes 9 + t bits; t = 7 is bf16 and t = 23 is fp32. A block takes the
+   smallest t in [7, 23] whose u passes eq:amp_prec_choice (ties pass), else
+   fp64. Rounding stays elementwise relative, so eq:need_mvp and Thm amp hold
+   with the block's u as for the fixed formats.
 """
 from __future__ import annotations
 
@@ -71,6 +78,10 @@ UNIT = {FMT_FP64: 2.0 ** -53, FMT_FP32: 2.0 ** -24, FMT_FP16: 2.0 ** -11,
 BITS = {FMT_FP64: 64, FMT_FP32: 32, FMT_FP16: 16, FMT_BF16: 16, FMT_Q43: 8}
 # q43 (R10): 4 significant bits, normal exponents -6..7, largest value 240.
 Q43_EMIN, Q43_EMAX, Q43_SIG = -6, 7, 4
+# Continuum storage (R11): a float with an 8-bit exponent and t fraction bits,
+# CONT_TMIN <= t <= CONT_TMAX, chosen per block; 9 + t bits per entry.
+FMT_CONT = 5
+CONT_TMIN, CONT_TMAX = 7, 23
 
 # Block types.
 T_FAR, T_NEAR, T_WEAK, T_DIAG, T_DENSE_NEAR = 0, 1, 2, 3, 4
@@ -536,6 +547,24 @@ def round_q43(x: np.ndarray) -> np.ndarray:
     return out
 
 
+def round_fp(x: np.ndarray, t: int) -> np.ndarray:
+    """Nearest value (ties to even) with t fraction bits and exponents >= -126
+    (gradual underflow below 2^-126); magnitudes that round beyond
+    (2 - 2^-t) 2^127 become inf (R11)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = x != 0.0
+    ax = np.abs(x[nz])
+    _, q = np.frexp(ax)
+    e = np.maximum(q - 1, -126)
+    ulp = np.ldexp(1.0, e - t)
+    r = np.rint(ax / ulp) * ulp
+    out[nz] = np.sign(x[nz]) * r
+    top = (2.0 - 2.0 ** -t) * 2.0 ** 127
+    out[np.abs(out) > top] = np.sign(out[np.abs(out) > top]) * np.inf
+    return out
+
+
 def q43_bits(v: np.ndarray) -> np.ndarray:
     """uint8 codes (sign, biased exponent, fraction) of q43 values held exactly
     in float64; exponent field 0 holds the subnormals."""
@@ -628,15 +657,29 @@ def choose_format(nb2: float, total2: float, level: int, d: int, eps: float,
     return FMT_FP64
 
 
+def choose_fraction_bits(nb2: float, total2: float, level: int, d: int, eps: float,
+                         tmin: int = CONT_TMIN, tmax: int = CONT_TMAX):
+    """Continuum rule (R11): the smallest t in [tmin, tmax] whose unit roundoff
+    2^-(t+1) passes eq:amp_prec_choice, or None when even tmax fails (fp64)."""
+    rhs = (eps * eps) * total2
+    for t in range(tmin, tmax + 1):
+        u = 2.0 ** -(t + 1)
+        if ((u * u) * (2.0 ** (d * level))) * nb2 <= rhs:
+            return t
+    return None
+
+
 def format_margin(nb2: float, total2: float, level: int, d: int, eps: float, fmt: int) -> float:
     """Ratio lhs / rhs of the precision test for `fmt` (1.0 is an exact tie)."""
     u = UNIT[fmt]
     return ((u * u) * (2.0 ** (d * level))) * nb2 / ((eps * eps) * total2)
 
 
-def beneficial(rank: int, m: int, n: int, fmt: int) -> bool:
-    """Low-rank storage of a leaf neighbour beats dense fp64 (Sec. 4.3 remark)."""
-    return rank * (m + n) * BITS[fmt] / 64.0 < m * n
+def beneficial(rank: int, m: int, n: int, fmt: int, bits: int | None = None) -> bool:
+    """Low-rank storage of a leaf neighbour beats dense fp64 (Sec. 4.3 remark);
+    `bits` overrides the format's width (continuum storage)."""
+    b = BITS[fmt] if bits is None else bits
+    return rank * (m + n) * b / 64.0 < m * n
 
 
 # --------------------------------------------------------------------------
@@ -660,6 +703,17 @@ class StoredBlock:
     D: np.ndarray | None = None       # dense block (m, n) float64
     nb2: float = 0.0                  # ||H~_b||^2 (truncated) or ||H_b||^2 (dense)
     comp: Compressed | None = None
+    t: int = -1                       # fraction bits when fmt == FMT_CONT
+
+
+def block_unit(sb: StoredBlock) -> float:
+    """Unit roundoff of a stored low-rank block's format."""
+    return 2.0 ** -(sb.t + 1) if sb.fmt == FMT_CONT else UNIT[sb.fmt]
+
+
+def block_bits(sb: StoredBlock) -> int:
+    """Bits per stored factor entry of a low-rank block."""
+    return 9 + sb.t if sb.fmt == FMT_CONT else BITS[sb.fmt]
 
 
 @dataclass
@@ -693,7 +747,7 @@ def block_entries(hm_points_tree: np.ndarray, kern: Kernel, normals_tree, b: Blo
 
 def build(points: np.ndarray, kern: Kernel, eps: float, eta: float, switch_level: int,
           leaf_size: int, mask: int = 0xF, uniform: bool = False, seed: int = 0,
-          keep_entries: bool = False) -> HMatrix:
+          keep_entries: bool = False, continuum: bool = False) -> HMatrix:
     tree = build_tree(points, leaf_size)
     ell = resolve_switch_level(switch_level, tree.L)
     blocks = partition(tree, eta, switch_level)
@@ -726,13 +780,28 @@ def build(points: np.ndarray, kern: Kernel, eps: float, eta: float, switch_level
         if not sb.lowrank:
             continue
         b = sb.blk
-        fmt = FMT_FP64 if uniform else choose_format(sb.nb2, total2, b.level, tree.d, eps, mask)
-        if b.kind == T_DENSE_NEAR and not beneficial(sb.rank, b.m, b.n, fmt):
+        t = -1
+        if uniform:
+            fmt = FMT_FP64
+        elif continuum:
+            tc = choose_fraction_bits(sb.nb2, total2, b.level, tree.d, eps)
+            fmt, t = (FMT_FP64, -1) if tc is None else (FMT_CONT, tc)
+        else:
+            fmt = choose_format(sb.nb2, total2, b.level, tree.d, eps, mask)
+        bits = 9 + t if fmt == FMT_CONT else None
+        if b.kind == T_DENSE_NEAR and not beneficial(sb.rank, b.m, b.n, fmt, bits):
             sb.lowrank = False
             sb.nb2 = float(np.sum(sb.D * sb.D))
             sb.Ut = sb.Vt = None
             continue
         sb.fmt = fmt
+        sb.t = t
+        if fmt == FMT_CONT:
+            sb.U, sb.Uraw, sb.eU = round_fp(sb.Ut, t), None, 0
+            sb.V, sb.Vraw, sb.eV = round_fp(sb.Vt, t), None, 0
+            if b.kind == T_DENSE_NEAR:
+                sb.D = None
+            continue
         sb.U, sb.Uraw, sb.eU = quantize(sb.Ut, fmt)
         sb.V, sb.Vraw, sb.eV = quantize(sb.Vt, fmt)
         sb.U = np.ldexp(sb.U, sb.eU)
@@ -811,11 +880,11 @@ def storage(hm: HMatrix) -> dict:
     """Words of 64 bits: low-rank p(|I|+|J|) b/64 plus dense m n."""
     lr = 0.0
     dense = 0.0
-    by_fmt = {f: 0 for f in UNIT}
+    by_fmt = {f: 0 for f in list(UNIT) + [FMT_CONT]}
     for sb in hm.blocks:
         b = sb.blk
         if sb.lowrank:
-            lr += sb.rank * (b.m + b.n) * BITS[sb.fmt] / 64.0
+            lr += sb.rank * (b.m + b.n) * block_bits(sb) / 64.0
             by_fmt[sb.fmt] += 1
         else:
             dense += b.m * b.n
@@ -855,7 +924,7 @@ def block_words(sb: StoredBlock) -> float:
     """64-bit words of one stored block: k (m + n) bits / 64 low rank, m n dense."""
     b = sb.blk
     if sb.lowrank:
-        return sb.rank * (b.m + b.n) * BITS[sb.fmt] / 64.0
+        return sb.rank * (b.m + b.n) * block_bits(sb) / 64.0
     return float(b.m * b.n)
 
 
