@@ -212,7 +212,8 @@ hh_status hh_matvec_timed(const hh_handle* h, const void* x, void* y, int64_t nr
  * repeated call only uploads the x / y descriptors on `stream` and returns
  * without waiting. Calls that overlap in time (other streams, other threads)
  * share that descriptor table and the handles' workspaces, and race. Freeing
- * a handle of the batch drops the tables. */
+ * a handle of the batch drops the tables. The descriptor upload is a copy from
+ * pageable host memory, so this call must not be recorded into a HIP graph. */
 hh_status hh_matvec_batch(const hh_handle* const* hs, int count, const void* const* x,
                           void* const* y, int64_t nrhs, void* stream);
 
