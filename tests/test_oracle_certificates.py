@@ -102,3 +102,33 @@ def test_beneficial_storage_is_strict():
     assert not O.beneficial(64, 64, 64, W.FMT_FP32)
     assert O.beneficial(63, 64, 64, W.FMT_FP32)
     assert not O.beneficial(128, 64, 64, W.FMT_BF16) and O.beneficial(127, 64, 64, W.FMT_BF16)
+
+
+def test_global_bound_matches_the_printed_forms():
+    # eq:error_bound_2d / eq:error_bound_3d (eta = sqrt d) for 1 <= ell <= L;
+    # ell = 0 is the HODLR case, where C'' drops out
+    for L in range(1, 7):
+        for ell in range(1, L + 1):
+            assert math.isclose(O.global_bound(2, math.sqrt(2), L, ell),
+                                2 * math.sqrt(27 * ell + 8 + 3 * (L - ell)) + 1, rel_tol=1e-15)
+            assert math.isclose(O.global_bound(3, math.sqrt(3), L, ell),
+                                2 * math.sqrt(189 * ell + 26 + 7 * (L - ell)) + 1, rel_tol=1e-15)
+        assert math.isclose(O.global_bound(3, math.sqrt(3), L, 0), 2 * math.sqrt(7 * L) + 1, rel_tol=1e-15)
+    # the formula constants of eq:standard_IL_size / eq:standard_N_size at eta = sqrt d
+    for d, want in ((2, (27, 8, 3)), (3, (189, 26, 7))):
+        got = O.constants_formula(d, math.sqrt(d))
+        assert all(math.isclose(g, w, rel_tol=1e-12) for g, w in zip(got, want)), (d, got)
+
+
+def test_alg5_norm_does_not_depend_on_the_storage_decision():
+    # with ell = L, Alg. 5 takes the leaf neighbours' norms from their entries
+    # before Alg. 3 decides whether factors are stored: the mixed scheme (some
+    # neighbours compressed) and the uniform one (all dense) share ||H~||^2
+    rng = np.random.default_rng(77)
+    P = rng.random((1500, 2))
+    k = O.Kernel(W.INV_R)
+    hm = O.build(P, k, 1e-3, math.sqrt(2), 4, 8)
+    hu = O.build(P, k, 1e-3, math.sqrt(2), 4, 8, uniform=True)
+    assert hm.ell == hm.tree.L == 4
+    assert any(sb.lowrank and sb.blk.kind == O.T_DENSE_NEAR for sb in hm.blocks)
+    assert hm.total2 == hu.total2
