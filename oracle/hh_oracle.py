@@ -17,6 +17,8 @@ speed, following the paper's steps in its order:
 * fast Frobenius norms ......................... Alg. 5 (Appendix B)
 * adaptive precision choice .................... eq:amp_prec_choice, Alg. 3
 * mat-vec with the mixed-precision matrix ..... Alg. 4
+* switching-level choice ....................... eq:S1, eq:S2, Alg. 2 (Sec. 3.3)
+* q43 and continuum storage (R10, R11) ......... Table tab:precisions, Sec. 4.3
 * error bounds ................................. Lemma global_error, Thm amp,
                                                  Thm mvp, eq:standard_IL_size,
                                                  eq:standard_N_size, eq:weak_IL_size
