@@ -289,7 +289,7 @@ class Block:
 
 
 def resolve_switch_level(switch_level: int, L: int) -> int:
-    """switch_level = -1 selects the paper's default L - 1 (Sec. 3.2)."""
+    """switch_level = -1 selects the paper's default L - 1 (Sec. 3.3)."""
     if switch_level == -1:
         return max(L - 1, 0)
     return switch_level
