@@ -1,10 +1,9 @@
 """HIP-graph capture of the single-handle product (hh_matvec / hh_matvec_t with
 a workspace sized beforehand by hh_reserve).
 
-Not collected by pytest until it has passed on the GPU; run it by naming this
-file. The captured product is replayed several times, with new inputs copied
-into the captured buffer and ordinary eager work between replays, and every
-replay must equal an eager product bit for bit (products are deterministic)."""
+The captured product is replayed several times, with new inputs copied into
+the captured buffer and ordinary eager work between replays, and every replay
+must equal an eager product bit for bit (products are deterministic)."""
 import numpy as np
 import pytest
 
