@@ -9,13 +9,22 @@ stored uniformly in fp64 are timed beside it (built once; the adaptive handle
 is derived from it, so both hold identical factors before rounding).
 
 One step = one product y = H^ x (gather, inner products, leaf accumulation),
-inputs resident in HBM. Prints one JSON line; `value` is adaptive matvec/s.
-The roofline object covers the kernel with the largest share of the step
-time, with its algorithmic bytes per launch over its mean event-timed
-duration in the timed region. The CPU baseline is the FP64 oracle's own
-product (Alg. 4) timed on the host on a smaller instance of the same recipe
-(N = 16384, leaf 256, L = 2), run in a child process while the GPU builds,
-and scaled to the headline by the ratio of stored entries.
+inputs resident in HBM. The product is recorded once into a HIP graph; after
+the warm-up replays, the K timed steps are K graph replays bracketed by device
+synchronisations, each also bracketed by events on the replay stream (their
+median is reported beside the wall-clock rate). `value` = adaptive products/s
+over the K timed replays. The roofline object covers the kernel with the
+largest share of the step: its algorithmic bytes per launch over its mean
+duration, from HIP events the library records around each of its kernels on
+the product's stream in K further eager products. The several-RHS rows
+(16 and 256 right-hand sides on the same adaptive handle) are timed the same
+way and carry an fp64-MFMA roofline each.
+
+The CPU baseline is the FP64 oracle's own product (Alg. 4) on a bounded
+sample of the same matrix, run in a child process while the GPU builds: the
+oracle builds the headline's tree and partition, compresses a sample of its
+blocks (every kind and level), times its product over those blocks and
+scales the per-entry time to all stored entries of the GPU's matrix.
 """
 from __future__ import annotations
 
@@ -34,7 +43,6 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6        # dense fp64 MFMA
-CPU_SAMPLE_N = 16384
 
 
 def measured_traffic(kernel: str, n: int, nrhs: int):
@@ -58,36 +66,152 @@ def measured_traffic(kernel: str, n: int, nrhs: int):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_worker(out_path: str, budget_s: float) -> None:
-    """Build the oracle on the sample instance and time its product."""
+def cpu_worker(out_path: str, budget_s: float, n: int) -> None:
+    """The oracle's product (Alg. 4) on a bounded sample of the benchmark
+    matrix. The oracle builds the tree and partition of the workload and
+    compresses a few blocks of each (level, kind) group; each group's blocks,
+    with their row and column ranges laid side by side in a short vector, form
+    a small H matrix that O.matvec applies repeatedly (its O(length) gather and
+    scatter, timed with no blocks, is subtracted). Level-2 blocks (16384^2, half
+    a minute each for the oracle to generate and compress) are not sampled:
+    their interaction-list rate is taken from the level-3 interaction list."""
+    import dataclasses
+
     import numpy as np
 
     import workloads as W
     from oracle import hh_oracle as O
+    cores = len(os.sched_getaffinity(0))
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=cores, user_api="blas")
     except Exception:
-        threads = 1
-    p = W.cfg_3d_laplace(n=CPU_SAMPLE_N)
+        pass
+    p = W.cfg_3d_laplace(n=n)
+    kern = O.Kernel(p.kernel, scale=p.scale)
     t0 = time.perf_counter()
-    hm = O.build(p.points, O.Kernel(p.kernel, scale=p.scale), p.tol, p.eta, -1, p.leaf_size)
-    t_build = time.perf_counter() - t0
-    x = W.rhs(p.n, 1, np.random.default_rng(1))[:, 0]
-    O.matvec(hm, x)
-    reps, t0 = 0, time.perf_counter()
-    while True:
+    tree = O.build_tree(p.points, p.leaf_size)
+    blocks = O.partition(tree, p.eta, p.switch_level)
+    pt = p.points[tree.perm]
+    rng = np.random.default_rng(7)
+    groups = {}
+    for q, b in enumerate(blocks):
+        if b.level >= tree.L - 1:
+            groups.setdefault((b.level, b.kind), []).append(q)
+    stored = {}
+    for key, qs in sorted(groups.items()):
+        pick = rng.choice(qs, min(3 if key[0] < tree.L else 16, len(qs)), replace=False)
+        sbs, off = [], 0
+        for q in sorted(int(v) for v in pick):
+            b = blocks[q]
+            H = O.block_entries(pt, kern, None, b)
+            # the block's rows and columns get their own slots of the short vector
+            nb = dataclasses.replace(b, ib=off, ie=off + b.m, jb=off + b.m, je=off + b.m + b.n)
+            off += b.m + b.n
+            if b.kind == O.T_DIAG:
+                sbs.append(O.StoredBlock(nb, q, False, D=H))
+            else:
+                c = O.compress(H, p.tol, p.seed, q)
+                sbs.append(O.StoredBlock(nb, q, True, rank=c.rank, U=c.U, V=c.V))
+        stored[key] = (sbs, off)
+    t_prep = time.perf_counter() - t0
+
+    def timed(sbs, length):
+        sub = O.Tree(length, tree.d, tree.L, np.arange(length), None, None)
+        hm = O.HMatrix(p.points, kern, sub, p.eta, p.switch_level, p.tol, 0xF, False, blocks=sbs)
+        x = W.rhs(length, 1, np.random.default_rng(1))[:, 0]
         O.matvec(hm, x)
+        reps, t1 = 0, time.perf_counter()
+        while True:
+            O.matvec(hm, x)
+            reps += 1
+            el = time.perf_counter() - t1
+            if el >= budget_s / (2 * len(stored)) and reps >= 3:
+                return el / reps, reps
+
+    out = {"cores": cores, "prep_seconds": t_prep, "groups": []}
+    for (level, kind), (sbs, length) in sorted(stored.items()):
+        t, reps = timed(sbs, length)
+        t_fix, _ = timed([], length)
+        entries = sum(sb.rank * (sb.blk.m + sb.blk.n) if sb.lowrank else sb.blk.m * sb.blk.n
+                      for sb in sbs)
+        out["groups"].append({"level": level, "kind": kind, "blocks": len(sbs), "entries": entries,
+                              "seconds": max(t - t_fix, 0.0), "reps": reps})
+    x = W.rhs(p.n, 1, np.random.default_rng(1))[:, 0]
+    hm0 = O.HMatrix(p.points, kern, tree, p.eta, p.switch_level, p.tol, 0xF, False, blocks=[])
+    reps, t1 = 0, time.perf_counter()
+    while reps < 5:
+        O.matvec(hm0, x)
         reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    entries = sum(sb.rank * (sb.blk.m + sb.blk.n) if sb.lowrank else sb.blk.m * sb.blk.n
-                  for sb in hm.blocks)
+    out["fixed_seconds"] = (time.perf_counter() - t1) / reps
     with open(out_path, "w") as f:
-        json.dump({"seconds_per_matvec": el / reps, "reps": reps, "entries": entries,
-                   "threads": threads, "build_seconds": t_build, "n": p.n, "L": hm.tree.L,
-                   "ell": hm.ell}, f)
+        json.dump(out, f)
+
+
+def cpu_baseline(w: dict, bl: dict, n: int) -> dict:
+    """Oracle products/s on the whole matrix: the O(N) gather / scatter of one
+    product plus, per (level, kind) group, the sampled seconds per stored entry
+    times the group's stored entries in the matrix (groups of coarser levels at
+    the rate of the sampled interaction list of the coarsest sampled level)."""
+    import numpy as np
+    lr = bl["lowrank"].astype(bool)
+    m = (bl["row_end"] - bl["row_begin"]).astype(np.float64)
+    nn = (bl["col_end"] - bl["col_begin"]).astype(np.float64)
+    ent = np.where(lr, bl["rank"] * (m + nn), m * nn)
+    rate = {(g["level"], g["kind"]): g["seconds"] / max(g["entries"], 1) for g in w["groups"]}
+    lmin = min(k[0] for k in rate)
+    far = rate.get((lmin, 0), max(rate.values()))
+    total = w["fixed_seconds"]
+    for lev, kind in set(zip(bl["level"].tolist(), bl["kind"].tolist())):
+        sel = (bl["level"] == lev) & (bl["kind"] == kind)
+        total += rate.get((lev, kind), far) * float(np.sum(ent[sel]))
+    parts = ", ".join(f"level {g['level']} kind {g['kind']}: {g['blocks']}" for g in w["groups"])
+    return {"value": 1.0 / total, "unit": "matvec/s", "cores": w["cores"], "kind": "oracle",
+            "sample": (f"oracle Alg. 4 product (O.matvec) over blocks of the N={n} matrix itself, "
+                       f"compressed by the oracle ({parts} blocks per group), each group applied "
+                       f"repeatedly on a vector holding just its rows and columns; seconds per stored "
+                       f"entry of each group times the group's stored entries in the matrix (levels "
+                       f"above {lmin} at the level-{lmin} interaction-list rate), plus the measured "
+                       f"O(N) gather/scatter ({w['fixed_seconds'] * 1e3:.1f} ms); "
+                       f"{w['cores']} BLAS threads")}
+
+
+def graph_timing(H, x, y, steps: int, warmup: int):
+    """Record one product into a HIP graph and replay it: (wall seconds of the
+    `steps` timed replays, median replay ms from events on the replay stream)."""
+    import torch
+    H.reserve(1 if x.dim() == 1 else x.shape[1])
+    H.matvec(x, out=y)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        H.matvec(x, out=y)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        graph.replay()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sorted(a.elapsed_time(b) for a, b in evs)
+    del graph
+    return wall, ms[len(ms) // 2]
+
+
+def phase_timing(H, x, y, steps: int):
+    """Mean [gather, inner products, leaf accumulation] ms over `steps` eager
+    products with the library's per-kernel HIP events."""
+    import numpy as np
+    ph = np.zeros(3)
+    for _ in range(steps):
+        _, ms = H.matvec_timed(x, out=y)
+        ph += ms
+    return ph / steps
 
 
 def switch_level_bench(n: int) -> int:
@@ -126,11 +250,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--multi-rhs", default="16,256",
+                    help="right-hand-side counts timed on the adaptive handle after the "
+                         "single-vector product ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uniform", action="store_true", help="build the adaptive handle only")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--switch-level", action="store_true",
@@ -138,7 +264,7 @@ def main() -> int:
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
-        cpu_worker(args.cpu_worker, args.cpu_budget)
+        cpu_worker(args.cpu_worker, args.cpu_budget, args.n)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU: the H_h product here runs on a single MI355X "
@@ -146,6 +272,7 @@ def main() -> int:
         return 2
     if args.switch_level:
         return switch_level_bench(args.n)
+    multi = [int(v) for v in args.multi_rhs.split(",") if v.strip()]
 
     # CPU baseline in a child process, overlapped with the GPU build
     worker = None
@@ -154,7 +281,8 @@ def main() -> int:
         fd, wpath = tempfile.mkstemp(prefix="hh_cpu_", suffix=".json")
         os.close(fd)
         worker = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", wpath,
-                                   "--cpu-budget", str(args.cpu_budget)], cwd=ROOT)
+                                   "--cpu-budget", str(args.cpu_budget), "--n", str(args.n)],
+                                  cwd=ROOT)
 
     import numpy as np
     import torch
@@ -178,43 +306,60 @@ def main() -> int:
     t_build = time.perf_counter() - t0
     print(f"bench: built in {t_build:.1f} s", file=sys.stderr, flush=True)
 
-    x = torch.from_numpy(W.rhs(p.n, args.nrhs, np.random.default_rng(1))).cuda()
-    if args.nrhs == 1:
-        x = x[:, 0].contiguous()
+    x = torch.from_numpy(W.rhs(p.n, 1, np.random.default_rng(1))[:, 0].copy()).cuda()
 
-    def run(H):
-        y = torch.empty_like(x)
-        for _ in range(args.warmup):
-            H.matvec(x, out=y)
+    def run(H, xin):
+        y = torch.empty_like(xin)
+        wall, med = graph_timing(H, xin, y, args.steps, args.warmup)
+        ph = phase_timing(H, xin, y, args.steps)
         torch.cuda.synchronize()
-        ph = np.zeros(3)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, ms = H.matvec_timed(x, out=y)
-            ph += ms
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        return y, el, ph / args.steps
+        return y.clone(), wall, med, ph
 
-    ya, el_a, ph_a = run(Ha)
+    ya, el_a, med_a, ph_a = run(Ha, x)
     sa = Ha.stats()
+    print(f"bench: adaptive {1e3 * el_a / args.steps:.3f} ms per product", file=sys.stderr, flush=True)
     res = {"adaptive": {"matvec_per_s": args.steps / el_a, "ms_per_step": 1000 * el_a / args.steps,
+                        "graph_replay_ms_median": round(med_a, 4),
                         "phase_ms": [round(v, 4) for v in ph_a],
                         "phase_bytes": [int(v) for v in sa["phase_bytes"]],
                         "bytes_per_matvec": sa["matvec_bytes"],
                         "hbm_gbs": sa["matvec_bytes"] / (el_a / args.steps) / 1e9,
                         "blocks_by_format": sa["blocks_by_format"]}}
     if H64 is not None:
-        y6, el_6, ph_6 = run(H64)
+        y6, el_6, med_6, ph_6 = run(H64, x)
         s6 = H64.stats()
         res["uniform_fp64"] = {"matvec_per_s": args.steps / el_6,
                                "ms_per_step": 1000 * el_6 / args.steps,
+                               "graph_replay_ms_median": round(med_6, 4),
                                "phase_ms": [round(v, 4) for v in ph_6],
                                "phase_bytes": [int(v) for v in s6["phase_bytes"]],
                                "bytes_per_matvec": s6["matvec_bytes"],
                                "hbm_gbs": s6["matvec_bytes"] / (el_6 / args.steps) / 1e9}
         res["speedup_vs_uniform_fp64"] = el_6 / el_a
         res["adaptive_vs_uniform_rel_diff"] = float(torch.linalg.norm(ya - y6) / torch.linalg.norm(y6))
+        # continuum storage (per block t fraction bits) of the same factors
+        Hc = H64.derive(continuum=True)
+        yc, el_c, med_c, ph_c = run(Hc, x)
+        sc = Hc.stats()
+        bc = Hc.blocks()
+        tb = bc["frac_bits"][bc["format"] == 4]
+        res["continuum"] = {"matvec_per_s": args.steps / el_c, "ms_per_step": 1000 * el_c / args.steps,
+                            "graph_replay_ms_median": round(med_c, 4),
+                            "phase_ms": [round(v, 4) for v in ph_c],
+                            "phase_bytes": [int(v) for v in sc["phase_bytes"]],
+                            "bytes_per_matvec": sc["matvec_bytes"],
+                            "hbm_gbs": sc["matvec_bytes"] / (el_c / args.steps) / 1e9,
+                            "blocks_by_format": sc["blocks_by_format"],
+                            "fraction_bits_histogram": {int(v): int(np.sum(tb == v)) for v in np.unique(tb)},
+                            "speedup_vs_uniform_fp64": el_6 / el_c,
+                            "rel_diff_vs_uniform_fp64": float(torch.linalg.norm(yc - y6) /
+                                                              torch.linalg.norm(y6))}
+        print(f"bench: continuum {1e3 * el_c / args.steps:.3f} ms per product", file=sys.stderr, flush=True)
+        Hc.free()
+        del yc
+        H64.free()
+        del y6
+        torch.cuda.empty_cache()
 
     if args.copy_check:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
@@ -226,28 +371,46 @@ def main() -> int:
         del a, b
 
     k = int(np.argmax(ph_a))
-    if args.nrhs == 1:
-        names = ["gather", "column inner products (dot1_kernel)",
-                 "leaf accumulation (unit_kernel + finish_kernel)"]
-        kernels = ["gather_kernel", "dot1_kernel", "accumulation"]
-        achieved = sa["phase_bytes"][k] / (ph_a[k] / 1e3) / 1e9
-        roofline = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(kernels[k], p.n, args.nrhs)}
-    else:
-        # several right-hand sides: fp64 MFMA contractions, 2 R flops per stored
-        # entry (phase V: V entries; phase U: U entries and dense entries)
-        names = ["gather", "column inner products (dotm_kernel)", "leaf accumulation (accm_kernel)"]
-        bl = Ha.blocks()
+    names = ["gather", "column inner products (dot1_kernel)",
+             "leaf accumulation (unit_kernel + finish_kernel)"]
+    kernels = ["gather_kernel", "dot1_kernel", "accumulation"]
+    achieved = sa["phase_bytes"][k] / (ph_a[k] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kernels[k], p.n, 1)}
+
+    # several right-hand sides on the adaptive handle: fp64 MFMA contractions,
+    # 2 R flops per stored entry (phase V: V entries; phase U: U and dense entries)
+    bl = Ha.blocks()
+    if multi:
         lrm = bl["lowrank"].astype(bool)
         rk = bl["rank"].astype(np.float64)
         v_entries = float(np.sum((rk * (bl["col_end"] - bl["col_begin"]))[lrm]))
         u_entries = float(np.sum((rk * (bl["row_end"] - bl["row_begin"]))[lrm]))
-        flops = [0.0, 2.0 * args.nrhs * v_entries, 2.0 * args.nrhs * (u_entries + sa["dense_entries"])]
-        achieved = flops[k] / (ph_a[k] / 1e3) / 1e12
-        roofline = {"bound": "mfma", "kernel": names[k], "achieved": round(achieved, 2),
-                    "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFS, 4),
-                    "traffic": None}
+        for R in multi:
+            X = torch.from_numpy(W.rhs(p.n, R, np.random.default_rng(R))).cuda()
+            Y, el_r, med_r, ph_r = run(Ha, X)
+            col = int(np.random.default_rng(R + 1).integers(R))
+            y1 = Ha.matvec(X[:, col].contiguous())
+            flops = [0.0, 2.0 * R * v_entries, 2.0 * R * (u_entries + sa["dense_entries"])]
+            kr = int(np.argmax(ph_r))
+            ach = flops[kr] / (ph_r[kr] / 1e3) / 1e12
+            total_tf = (flops[1] + flops[2]) / (el_r / args.steps) / 1e12
+            res[f"adaptive_nrhs{R}"] = {
+                "products_per_s": args.steps / el_r, "ms_per_step": 1000 * el_r / args.steps,
+                "rhs_products_per_s": R * args.steps / el_r,
+                "graph_replay_ms_median": round(med_r, 4),
+                "phase_ms": [round(v, 4) for v in ph_r], "tflops_whole_product": round(total_tf, 2),
+                "column_vs_single_rhs_rel_diff": float(torch.linalg.norm(Y[:, col] - y1) /
+                                                       torch.linalg.norm(y1)),
+                "roofline": {"bound": "mfma", "kernel": ["gather", "column inner products (dotm_kernel)",
+                                                         "leaf accumulation (accm_kernel)"][kr],
+                             "achieved": round(ach, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                             "frac": round(ach / FP64_PEAK_TFS, 4), "traffic": None}}
+            print(f"bench: adaptive, {R} RHS: {1e3 * el_r / args.steps:.3f} ms per product",
+                  file=sys.stderr, flush=True)
+            del X, Y, y1
+            torch.cuda.empty_cache()
 
     cpu = None
     if worker is not None:
@@ -255,14 +418,7 @@ def main() -> int:
             worker.wait(timeout=900)
             with open(wpath) as f:
                 w = json.load(f)
-            headline_entries = sa["lowrank_entries"] + sa["dense_entries"]
-            per_entry = w["seconds_per_matvec"] / w["entries"]
-            cpu = {"value": 1.0 / (per_entry * headline_entries), "unit": "matvec/s",
-                   "cores": w["threads"], "kind": "oracle",
-                   "sample": (f"oracle Alg. 4 product on its own H_h of the same recipe at N={w['n']} "
-                              f"(L={w['L']}, switch {w['ell']}): {w['seconds_per_matvec']*1e3:.2f} ms per "
-                              f"product over {w['entries']} stored entries, {w['reps']} products; scaled "
-                              f"to the {headline_entries} stored entries of the N={p.n} matrix")}
+            cpu = cpu_baseline(w, bl, p.n)
         except Exception as e:  # the baseline is reported, never required
             cpu = {"value": None, "unit": "matvec/s", "cores": None, "kind": "oracle",
                    "sample": f"unavailable: {e}"}
@@ -278,9 +434,9 @@ def main() -> int:
            "data": "synthetic (seeded uniform points, x ~ N(0,1))",
            "config": {"workload": f"3D Laplace 1/(4 pi r), N={p.n} uniform in [0,1]^3, leaf "
                                   f"{p.leaf_size}, eta {p.eta}, switch level {p.switch_level}, tol "
-                                  f"{p.tol}, adaptive fp64/fp32/fp16/bf16, nrhs {args.nrhs}",
-                      "n": p.n, "nrhs": args.nrhs, "build_seconds": round(t_build, 2),
-                      "parallelism": "1 GPU"},
+                                  f"{p.tol}, adaptive fp64/fp32/fp16/bf16, nrhs 1",
+                      "n": p.n, "nrhs": 1, "build_seconds": round(t_build, 2),
+                      "timing": "graph replays", "parallelism": "1 GPU"},
            "hbm_gbs": round(res["adaptive"]["hbm_gbs"], 1), "results": res,
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

@@ -59,8 +59,12 @@ typedef enum {
     HH_DOUBLE_LAYER = 6
 } hh_kernel_type;
 
-/* Storage formats of Table tab:precisions used for the low-rank factors. */
-enum { HH_FMT_FP64 = 0, HH_FMT_FP32 = 1, HH_FMT_FP16 = 2, HH_FMT_BF16 = 3 };
+/* Storage formats of Table tab:precisions used for the low-rank factors, and
+ * the continuum format of the accessor remark of Sec. 4.3: per block t
+ * fraction bits (7 <= t <= 23) behind a sign and an 8-bit exponent with fp32's
+ * range and gradual underflow, 9 + t bits per entry, round to nearest even
+ * (t = 7 is bf16, t = 23 fp32). */
+enum { HH_FMT_FP64 = 0, HH_FMT_FP32 = 1, HH_FMT_FP16 = 2, HH_FMT_BF16 = 3, HH_FMT_CONT = 4 };
 /* Element type of x and y in the products. */
 enum { HH_IO_F64 = 0, HH_IO_F32 = 1 };
 
@@ -87,6 +91,10 @@ typedef struct {
                                 and ranks); the uniform-precision baseline        */
     int io_dtype;            /* HH_IO_F64 (default) or HH_IO_F32 for x and y       */
     uint64_t seed;           /* key of the randomized-compression sketches          */
+    int continuum;           /* 1: continuum storage (HH_FMT_CONT) instead of the
+                                mask's formats: each block takes the fewest
+                                fraction bits t in [7, 23] whose unit roundoff
+                                2^-(t+1) passes the rule, else fp64             */
 } hh_options;
 
 typedef struct {
@@ -95,8 +103,8 @@ typedef struct {
     int64_t n_blocks_lowrank;             /* low-rank blocks with rank > 0             */
     int64_t n_blocks_rank0;               /* admissible blocks compressed to rank 0    */
     int64_t n_blocks_dense;               /* dense blocks (diagonal + dense neighbours) */
-    int64_t blocks_by_format[4];          /* low-rank blocks per HH_FMT_*              */
-    int64_t factor_bytes_by_format[4];    /* device bytes of U and V per format        */
+    int64_t blocks_by_format[5];          /* low-rank blocks per HH_FMT_*              */
+    int64_t factor_bytes_by_format[5];    /* device bytes of U and V per format        */
     int64_t dense_bytes;                  /* device bytes of dense blocks (fp64)       */
     int64_t lowrank_entries;              /* sum_b k_b (m_b + n_b)                     */
     int64_t dense_entries;                /* sum m n over dense blocks                 */
@@ -105,7 +113,8 @@ typedef struct {
                                              sum k (m + n) b / 64 + sum m n (Sec. 5.2)  */
     double storage_words_fp64;            /* the same with every factor in fp64        */
     double matvec_bytes;                  /* algorithmic HBM bytes of one nrhs = 1
-                                             product: factors + dense + x + y          */
+                                             product: factors (k (m + n) bits / 8 per
+                                             block) + dense + x + y                    */
     double norm2_total;                   /* ||H~||_F^2 from Alg. 5                    */
     double build_seconds;                 /* wall time of hh_build / hh_derive         */
     double phase_bytes[3];                /* algorithmic HBM bytes of the three kernels
@@ -122,6 +131,7 @@ typedef struct {                          /* one block, canonical order (level, 
     int64_t col_begin, col_end;           /* column range in tree order               */
     int32_t exp_u, exp_v;                 /* stored factor = value * 2^-exp            */
     int32_t lowrank;                      /* 1 = U V^T factors, 0 = dense              */
+    int32_t frac_bits;                    /* t of an HH_FMT_CONT block, else 0         */
     double norm2;                         /* ||H~_b||^2 (truncated) or ||H_b||^2        */
     double entry_norm2;                   /* ||H_b||_F^2 summed from the entries       */
     double tail_prev, tail;               /* discarded tail at rank-1 and at rank      */
@@ -134,6 +144,12 @@ typedef struct {                          /* one block, canonical order (level, 
  * truncated-SVD compression with accuracy tol per admissible block, Def. of
  * H_h(p, eps)), Alg. 5 (norms from singular values) and Alg. 3 (per-block
  * storage precision: the largest unit roundoff u <= tol / (2^(d l / 2) xi_b)).
+ * Blocks with min(m, n) <= 512 take the truncated SVD itself; larger blocks a
+ * randomized range finder (Rademacher sketch keyed by opt->seed, one power
+ * iteration) whose discarded tail includes the directly summed residual
+ * ||H_b - Q Q^T H_b||_F^2, so ||H_b - U_b V_b^T||_F <= tol ||H_b||_F holds for
+ * every block. HH_ENOTSUP if one factor column would span 2^31 bytes or more
+ * (the product kernels address factors with 32-bit offsets).
  *   points        HOST, n x d row-major float64; copied.
  *   n             number of points, >= 1.     d in {1, 2, 3}.
  *   k             kernel description (not NULL).
@@ -193,8 +209,10 @@ hh_status hh_switch_level_search(const double* points, int64_t n, int d, const h
  * results are bitwise reproducible run to run.  nrhs >= 1. */
 hh_status hh_matvec(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream);
 
-/* hh_matvec_t: y = H^^T x: y_J += V_b (U_b^T x_I), y_J += H_IJ^T x_I (dense
- * blocks transposed inside the kernel). Same conventions as hh_matvec. */
+/* hh_matvec_t: y = H^^T x: y_J += V_b (U_b^T x_I), y_J += H_IJ^T x_I. The
+ * dense blocks of H^T are applied from transposed copies that hh_build stores
+ * beside the originals (fp64, 8 sum n_i^2 extra bytes), so the transpose runs
+ * the same kernels as the forward product. Same conventions as hh_matvec. */
 hh_status hh_matvec_t(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream);
 
 /* hh_matvec_timed: one product (trans = 0: H^ x, 1: H^^T x) exactly as
@@ -216,6 +234,29 @@ hh_status hh_matvec_timed(const hh_handle* h, const void* x, void* y, int64_t nr
  * pageable host memory, so this call must not be recorded into a HIP graph. */
 hh_status hh_matvec_batch(const hh_handle* const* hs, int count, const void* const* x,
                           void* const* y, int64_t nrhs, void* stream);
+
+/* Bytes of the fixed device array behind hh_matvec_noalloc (one per device). */
+#define HH_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* hh_matvec_noalloc: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). The product of hh_matvec (trans = 0) or hh_matvec_t (trans = 1),
+ * with the same kernels and bit for bit the same result, but its workspace
+ * (gathered x, the nrhs coefficients of every stored column, and for nrhs = 1
+ * the partial rows of the work units) lives in a fixed device array of
+ * HH_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it runs
+ * on until the process ends, not in the handle. The call allocates nothing and
+ * never grows the handle's workspace. It needs 8 nrhs (Np + C) bytes, plus
+ * 8 Q bytes when nrhs = 1, each part rounded up to 256 bytes (Np = N padded to
+ * 4 rows per leaf, C = sum_b k_b = hh_stats.total_columns, Q = partial rows,
+ * about 2 N at leaf 256); a product needing more returns HH_ENOTSUP with
+ * nothing queued. Every call on one device shares that array and nothing in it
+ * needs clearing between calls: calls in one stream order are safe, calls
+ * that overlap in time on one device (other streams or threads, replays of
+ * captured graphs on several streams) race and give wrong results. Arguments
+ * and other errors as for hh_matvec. */
+hh_status hh_matvec_noalloc(const hh_handle* h, const void* x, void* y, int64_t nrhs, int trans,
+                            void* stream);
 
 /* hh_reserve: size the product workspace for up to max_nrhs right-hand sides
  * now (products with larger nrhs allocate on first use, which is not allowed
@@ -260,6 +301,13 @@ void hh_plan_free(hh_plan* p);
  * to every factor (e = 0 for fp64 / fp32; the build picks e per factor so that
  * the largest entry lands in [2^14, 2^15) for fp16 and in [1, 2) for bf16). */
 hh_status hh_quantize(const double* in, int64_t n, int format, int e, double* out);
+
+/* hh_quantize_cont: the continuum storage rounding on the host: out[i] = the
+ * nearest value (ties to even) with t fraction bits (7 <= t <= 23), fp32's
+ * exponent range and gradual underflow below 2^-126; magnitudes rounding past
+ * (2 - 2^-t) 2^127 become infinite. The arithmetic hh_build applies to every
+ * factor of an HH_FMT_CONT block (the accessor remark of Sec. 4.3). */
+hh_status hh_quantize_cont(const double* in, int64_t n, int t, double* out);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* hh_last_error(void);

@@ -1,7 +1,8 @@
 """torch.autograd.Function over the H_h product: forward y = H^ x, backward
 grad_x = H^^T grad_y (the transposed product: roles of U_b and V_b swapped,
-dense blocks transposed inside the kernel). Both directions run in the native
-library; torch only supplies tensors and the stream."""
+dense diagonal blocks applied from transposed copies stored at build time).
+Both directions run in the native library; torch only supplies tensors and the
+stream."""
 from __future__ import annotations
 
 import torch

@@ -3,10 +3,11 @@
 // values) and Alg. 3 (per-block storage precision), followed by the layout of
 // the product kernels' tasks.
 //
-// Compression: blocks with min(m, n) <= 512 use a full SVD; larger blocks use a
-// randomized range finder (Rademacher sketch keyed by (seed, block, round), one
-// power iteration, width 32 doubling while rank + 16 > width) whose truncation
-// error ||H - Q Q^T H||_F^2 is summed directly, so that every block satisfies
+// Compression: blocks with min(m, n) <= 512 take the truncated SVD of Sec. 2.2
+// (rocSOLVER's batched SVD of the whole block); larger blocks use a randomized
+// range finder (Rademacher sketch keyed by (seed, block, round), one power
+// iteration, width 64 doubling while rank + 16 > width) whose truncation error
+// ||H - Q Q^T H||_F^2 is summed directly, so that every block satisfies
 // ||H_b - U_b V_b^T||_F <= eps ||H_b||_F (Def. of H_h(p, eps)). Batches of
 // similar blocks run through rocBLAS / rocSOLVER strided-batched calls after
 // zero padding to the batch maximum (zero rows and columns change neither the
@@ -44,11 +45,23 @@ namespace hh {
                  std::string(#x) + ": rocblas status " + std::to_string((int)s_));         \
     } while (0)
 
-constexpr int EXACT_SVD_MAX = 64;
+constexpr int EXACT_SVD_MAX = 512;
 constexpr int SKETCH_START = 64;
 constexpr int OVERSAMPLE = 16;
 constexpr int64_t SUM_CHUNK = 65536;
 constexpr int64_t UNIT_BYTES = 1 << 20;   // factor bytes per single-vector work unit
+// The accumulation kernels address a run through one buffer descriptor with
+// 32-bit byte offsets, so a run (and every slice of one) spans fewer than 2^31
+// bytes: longer runs are cut by columns. HH_RUN_BYTES_MAX may lower the limit
+// (to exercise the cutting at small sizes).
+static int64_t run_bytes_max() {
+    int64_t lim = ((int64_t)1 << 31) - 1;
+    if (const char* e = getenv("HH_RUN_BYTES_MAX")) {
+        const long long v = atoll(e);
+        if (v > 0 && v < lim) lim = v;
+    }
+    return lim;
+}
 constexpr int64_t DOT_TASK_ELEMS = 65536;
 constexpr int64_t DOT_X_LDS = 4096;        // rows of x staged in LDS by dot1_kernel
 
@@ -84,6 +97,12 @@ void DevMem::free_all() {
 static size_t fmt_size(int fmt) { return fmt == HH_FMT_FP64 ? 8 : fmt == HH_FMT_FP32 ? 4 : 2; }
 static const double UNIT[4] = {0x1p-53, 0x1p-24, 0x1p-11, 0x1p-8};
 static const int BITS[4] = {64, 32, 16, 16};
+// Storage bits per entry of a block's format (continuum: 9 + t).
+static int entry_bits(int fmt, int t) { return fmt == HH_FMT_CONT ? 9 + t : BITS[fmt]; }
+// Device bytes of one stored column of P (padded) rows.
+static int64_t col_bytes(int fmt, int t, int64_t P) {
+    return fmt == HH_FMT_CONT ? cont_col_bytes(P, 9 + t) : P * (int64_t)fmt_size(fmt);
+}
 
 template <class T>
 static T* upload(DevMem& m, const std::vector<T>& v) {
@@ -775,16 +794,16 @@ struct Builder {
 
     // Alg. 3 storage: round every low-rank factor into its format's arena.
     void pack(bool in_place_ok = true) {
-        int64_t need[4] = {0, 0, 0, 0};
+        int64_t need[NFMT] = {0, 0, 0, 0, 0};            // bytes per format
         std::vector<int64_t> lr;
         for (size_t i = 0; i < h->blocks.size(); ++i) {
             const BlockRec& r = h->blocks[i];
             if (r.lowrank && r.rank > 0) {
                 lr.push_back((int64_t)i);
-                need[r.fmt] += (int64_t)r.rank * (r.PI + r.PJ);
+                need[r.fmt] += (int64_t)r.rank * (col_bytes(r.fmt, r.t, r.PI) + col_bytes(r.fmt, r.t, r.PJ));
             }
         }
-        bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0;
+        bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0 && need[4] == 0;
         h->all_fp64 = all64;
         if (all64 && in_place_ok) {
             // The fp64 store can serve as the arena as it is; it is re-laid in
@@ -792,9 +811,9 @@ struct Builder {
             // fits in free device memory with 4 GiB to spare.
             size_t fr = 0, tot = 0;
             HIPCHK(hipMemGetInfo(&fr, &tot));
-            if ((double)fr < (double)need[0] * 8.0 + (double)(4ull << 30)) return;
+            if ((double)fr < (double)need[0] + (double)(4ull << 30)) return;
         }
-        // exponents of the scaled formats
+        // exponents of the scaled formats (fp16, bf16)
         std::vector<double> mx(2 * lr.size(), 0.0);
         {
             std::vector<SumItem> items;
@@ -813,25 +832,26 @@ struct Builder {
                 HIPCHK(hipMemcpy(mx.data() + a, out, part.size() * 8, hipMemcpyDeviceToHost));
             }
         }
-        char* arena[4] = {nullptr, nullptr, nullptr, nullptr};
-        for (int f = 0; f < 4; ++f)
-            if (need[f]) arena[f] = static_cast<char*>(h->mem.alloc((size_t)need[f] * fmt_size(f) + 256, false));
+        char* arena[NFMT] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        for (int f = 0; f < NFMT; ++f)
+            if (need[f]) arena[f] = static_cast<char*>(h->mem.alloc((size_t)need[f] + 256, false));
         // Arena of a format: every U in (level, row box, column box) order, then
         // every V in (level, column box, row box) order, so that the factors
         // of one cluster and format follow each other (one strided matrix).
-        int64_t offU[4] = {0, 0, 0, 0}, offV[4] = {0, 0, 0, 0};
-        for (int64_t i : lr) offV[h->blocks[i].fmt] += (int64_t)h->blocks[i].rank * h->blocks[i].PI;
+        int64_t offU[NFMT] = {0, 0, 0, 0, 0}, offV[NFMT] = {0, 0, 0, 0, 0};
+        for (int64_t i : lr) {
+            const BlockRec& r = h->blocks[i];
+            offV[r.fmt] += (int64_t)r.rank * col_bytes(r.fmt, r.t, r.PI);
+        }
         std::vector<int64_t> lr_t(lr);
         std::stable_sort(lr_t.begin(), lr_t.end(), [&](int64_t x, int64_t y) {
             const Blk &a = h->blocks[x].b, &b = h->blocks[y].b;
             return std::make_tuple(a.level, a.bj, a.bi) < std::make_tuple(b.level, b.bj, b.bi);
         });
-        std::vector<PackItem> items;
-        int64_t maxcount = 0;
         for (size_t a = 0; a < lr.size(); ++a) {
             BlockRec& r = h->blocks[lr[a]];
             auto expo = [&](double m) {
-                if (r.fmt == HH_FMT_FP64 || r.fmt == HH_FMT_FP32 || m == 0.0) return 0;
+                if ((r.fmt != HH_FMT_FP16 && r.fmt != HH_FMT_BF16) || m == 0.0) return 0;
                 int q;
                 std::frexp(m, &q);
                 return r.fmt == HH_FMT_FP16 ? q - 1 - 14 : q - 1;
@@ -839,21 +859,33 @@ struct Builder {
             r.eU = expo(mx[2 * a]);
             r.eV = expo(mx[2 * a + 1]);
         }
+        std::vector<PackItem> items;
+        std::vector<ContPackItem> citems;
+        int64_t maxcount = 0, maxdw = 0;
+        auto add = [&](const BlockRec& r, const void* src, char* dst, int64_t P, int e) {
+            if (r.fmt == HH_FMT_CONT) {
+                const int64_t cdw = col_bytes(r.fmt, r.t, P) / 4;
+                citems.push_back(ContPackItem{(const double*)src, reinterpret_cast<uint32_t*>(dst), P,
+                                              cdw, r.rank, r.t});
+                maxdw = std::max(maxdw, (int64_t)r.rank * cdw);
+            } else {
+                items.push_back(PackItem{(const double*)src, dst, (int64_t)r.rank * P, r.fmt, e});
+                maxcount = std::max(maxcount, (int64_t)r.rank * P);
+            }
+        };
         std::vector<const void*> newU(h->blocks.size(), nullptr), newV(h->blocks.size(), nullptr);
         for (int64_t i : lr) {
             BlockRec& r = h->blocks[i];
-            char* up = arena[r.fmt] + offU[r.fmt] * fmt_size(r.fmt);
-            offU[r.fmt] += (int64_t)r.rank * r.PI;
-            items.push_back(PackItem{(const double*)r.u_ptr, up, (int64_t)r.rank * r.PI, r.fmt, r.eU});
-            maxcount = std::max(maxcount, (int64_t)r.rank * r.PI);
+            char* up = arena[r.fmt] + offU[r.fmt];
+            offU[r.fmt] += (int64_t)r.rank * col_bytes(r.fmt, r.t, r.PI);
+            add(r, r.u_ptr, up, r.PI, r.eU);
             newU[i] = up;
         }
         for (int64_t i : lr_t) {
             BlockRec& r = h->blocks[i];
-            char* vp = arena[r.fmt] + offV[r.fmt] * fmt_size(r.fmt);
-            offV[r.fmt] += (int64_t)r.rank * r.PJ;
-            items.push_back(PackItem{(const double*)r.v_ptr, vp, (int64_t)r.rank * r.PJ, r.fmt, r.eV});
-            maxcount = std::max(maxcount, (int64_t)r.rank * r.PJ);
+            char* vp = arena[r.fmt] + offV[r.fmt];
+            offV[r.fmt] += (int64_t)r.rank * col_bytes(r.fmt, r.t, r.PJ);
+            add(r, r.v_ptr, vp, r.PJ, r.eV);
             newV[i] = vp;
         }
         for (int64_t i : lr) {
@@ -865,6 +897,14 @@ struct Builder {
             std::vector<PackItem> part(items.begin() + a, items.begin() + e);
             Carver cv{scratch, scratch_bytes};
             launch_pack(meta(part, cv), (int)part.size(), maxcount, st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipDeviceSynchronize());
+        }
+        for (size_t a = 0; a < citems.size(); a += 32768) {
+            size_t e = std::min(citems.size(), a + 32768);
+            std::vector<ContPackItem> part(citems.begin() + a, citems.begin() + e);
+            Carver cv{scratch, scratch_bytes};
+            launch_pack_cont(meta(part, cv), (int)part.size(), maxdw, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipDeviceSynchronize());
         }
@@ -924,6 +964,15 @@ static std::vector<int64_t> direction_order(const hh_handle* h, bool trans) {
     return idx;
 }
 
+// Bytes between consecutive columns of a run, and of one column's slice of P
+// rows (continuum entries are w bits).
+static int64_t run_col_bytes(const Run& rn) {
+    return rn.fmt == HH_FMT_CONT ? (int64_t)rn.stride * 4 : (int64_t)rn.stride * (int64_t)fmt_size(rn.fmt);
+}
+static int64_t slice_bytes(const Run& rn, int64_t P) {
+    return rn.fmt == HH_FMT_CONT ? (P * rn.w + 7) / 8 : P * (int64_t)fmt_size(rn.fmt);
+}
+
 static void build_tasks(hh_handle* h) {
     const Plan& P = h->plan;
     const int L = P.L, d = P.d;
@@ -952,9 +1001,10 @@ static void build_tasks(hh_handle* h) {
     // transpose dots U with x_I into tb[col_t]; the factor scales go into tb
     for (const auto& r : h->blocks) {
         if (!(r.lowrank && r.rank > 0)) continue;
-        const size_t es = fmt_size(r.fmt);
+        const int wbits = r.fmt == HH_FMT_CONT ? 9 + r.t : 0;
         for (int pass = 0; pass < 2; ++pass) {
             const int64_t Pl = pass == 0 ? r.PJ : r.PI;
+            const int64_t cbytes = col_bytes(r.fmt, r.t, Pl);
             const char* base = static_cast<const char*>(pass == 0 ? r.v_ptr : r.u_ptr);
             // about DOT_TASK_ELEMS elements per task and at least one column per
             // wave; columns too long for the LDS stage of x go four to a wave
@@ -963,7 +1013,7 @@ static void build_tasks(hh_handle* h) {
                 r.rank, std::max<int64_t>(cmin, DOT_TASK_ELEMS / std::max<int64_t>(Pl, 1)));
             for (int64_t c0 = 0; c0 < r.rank; c0 += cpt) {
                 DotTask t{};
-                t.col0 = base + (size_t)(c0 * Pl) * es;
+                t.col0 = base + (size_t)(c0 * cbytes);
                 t.xoff = pass == 0 ? r.pJ : r.pI;
                 t.toff = (pass == 0 ? r.col : r.col_t) + c0;
                 t.P = (int32_t)Pl;
@@ -971,11 +1021,12 @@ static void build_tasks(hh_handle* h) {
                 t.fmt = r.fmt;
                 t.hid = 0;
                 t.exp = r.eU + r.eV;
+                t.w = wbits;
                 (pass == 0 ? F : T).dot.push_back(t);
             }
             for (int64_t c0 = 0; c0 < r.rank; c0 += 16 * DOTM_MT) {
                 DotTask t{};
-                t.col0 = base + (size_t)(c0 * Pl) * es;
+                t.col0 = base + (size_t)(c0 * cbytes);
                 t.xoff = pass == 0 ? r.pJ : r.pI;
                 t.toff = (pass == 0 ? r.col : r.col_t) + c0;
                 t.P = (int32_t)Pl;
@@ -983,6 +1034,7 @@ static void build_tasks(hh_handle* h) {
                 t.fmt = r.fmt;
                 t.hid = 0;
                 t.exp = r.eU + r.eV;
+                t.w = wbits;
                 (pass == 0 ? F : T).dotm.push_back(t);
             }
         }
@@ -1020,6 +1072,7 @@ static void build_tasks(hh_handle* h) {
             HIPCHK(hipDeviceSynchronize());
         }
     }
+    const int64_t run_lim = run_bytes_max();
     for (int dir = 0; dir < 2; ++dir) {
         TaskSet& S = dir == 0 ? F : T;
         const std::vector<int64_t>& ord = dir == 0 ? ord_f : ord_t;
@@ -1033,10 +1086,13 @@ static void build_tasks(hh_handle* h) {
                 if (r.rank == 0) continue;
                 rn.base = dir == 0 ? r.u_ptr : r.v_ptr;
                 rn.pc = dir == 0 ? r.pI : r.pJ;
-                rn.stride = (int32_t)(dir == 0 ? r.PI : r.PJ);
+                // stride in elements; for continuum columns in dwords
+                rn.stride = (int32_t)(r.fmt == HH_FMT_CONT ? col_bytes(r.fmt, r.t, dir == 0 ? r.PI : r.PJ) / 4
+                                                           : (dir == 0 ? r.PI : r.PJ));
                 rn.toff = (int32_t)(dir == 0 ? r.col : r.col_t);
                 rn.ncols = r.rank;
                 rn.fmt = (int8_t)r.fmt;
+                rn.w = (int16_t)(r.fmt == HH_FMT_CONT ? 9 + r.t : 0);
                 rn.from_x = 0;
             } else if (dir == 0) {
                 rn.base = r.d_ptr;
@@ -1055,29 +1111,40 @@ static void build_tasks(hh_handle* h) {
                 rn.fmt = HH_FMT_FP64;
                 rn.from_x = 1;
             }
-            // merge with the previous run when the columns continue it
+            // merge with the previous run when the columns continue it and the
+            // merged run stays under the buffer-offset limit
             std::vector<Run>& lst = per[ci];
+            const int64_t cb = run_col_bytes(rn);                                // bytes per column
+            if (cb > run_lim)
+                fail(HH_ENOTSUP, "a factor column spans more bytes than one buffer descriptor addresses");
+            const int64_t cmax = run_lim / cb;
             if (!lst.empty() && !rn.from_x) {
                 Run& pr = lst.back();
-                const char* end = static_cast<const char*>(pr.base) +
-                                  (size_t)pr.ncols * pr.stride * fmt_size(pr.fmt);
-                if (!pr.from_x && pr.fmt == rn.fmt && pr.stride == rn.stride && pr.pc == rn.pc &&
-                    end == rn.base && pr.toff + pr.ncols == rn.toff) {
+                const char* end = static_cast<const char*>(pr.base) + (size_t)pr.ncols * run_col_bytes(pr);
+                if (!pr.from_x && pr.fmt == rn.fmt && pr.w == rn.w && pr.stride == rn.stride && pr.pc == rn.pc &&
+                    end == rn.base && pr.toff + pr.ncols == rn.toff &&
+                    (int64_t)pr.ncols + rn.ncols <= cmax) {
                     pr.ncols += rn.ncols;
                     continue;
                 }
             }
-            lst.push_back(rn);
+            for (int64_t c0 = 0; c0 < rn.ncols; c0 += cmax) {
+                Run piece = rn;
+                piece.base = static_cast<const char*>(rn.base) + (size_t)(c0 * cb);
+                piece.toff = rn.toff + (int32_t)c0;
+                piece.ncols = (int32_t)std::min<int64_t>(cmax, rn.ncols - c0);
+                lst.push_back(piece);
+            }
         }
         // within a cluster, runs grouped by format (fp64, fp32, fp16, bf16)
-        S.cl_run.assign(4 * ncl + 1, 0);
+        S.cl_run.assign(NFMT * ncl + 1, 0);
         for (int64_t c = 0; c < ncl; ++c)
-            for (int f = 0; f < 4; ++f) {
-                S.cl_run[4 * c + f] = (int32_t)S.runs.size();
+            for (int f = 0; f < NFMT; ++f) {
+                S.cl_run[NFMT * c + f] = (int32_t)S.runs.size();
                 for (const Run& rn : per[c])
                     if (rn.fmt == f) S.runs.push_back(rn);
             }
-        S.cl_run[4 * ncl] = (int32_t)S.runs.size();
+        S.cl_run[NFMT * ncl] = (int32_t)S.runs.size();
         for (int64_t lf = 0; lf < nleaf; ++lf) {
             if (h->leaf_psz[lf] == 0) continue;
             LeafTask lt{};
@@ -1100,15 +1167,17 @@ static void build_tasks(hh_handle* h) {
             ft.leaf = lt.leaf;
             ft.hid = 0;
             std::vector<Run> list;                   // pieces in processing order
-            for (int f = 0; f < 4; ++f)
+            for (int f = 0; f < NFMT; ++f)
                 for (int l = 0; l <= L; ++l) {
                     const int64_t ci = first[l] + ((int64_t)lt.leaf >> (d * (L - l)));
                     for (const Run& rn : per[ci]) {
                         if (rn.fmt != f) continue;
-                        const int64_t colb = std::max<int64_t>(1, UNIT_BYTES / ((int64_t)lt.P * fmt_size(f)));
+                        const int64_t colb = std::max<int64_t>(
+                            1, std::min<int64_t>(UNIT_BYTES / std::max<int64_t>(slice_bytes(rn, lt.P), 1),
+                                                 run_lim / run_col_bytes(rn)));
                         for (int32_t c0 = 0; c0 < rn.ncols; c0 += (int32_t)colb) {
                             Run sub = rn;
-                            sub.base = static_cast<const char*>(rn.base) + (size_t)c0 * rn.stride * fmt_size(f);
+                            sub.base = static_cast<const char*>(rn.base) + (size_t)c0 * run_col_bytes(rn);
                             sub.toff = rn.toff + c0;
                             sub.ncols = (int32_t)std::min<int64_t>(colb, rn.ncols - c0);
                             list.push_back(sub);
@@ -1121,7 +1190,7 @@ static void build_tasks(hh_handle* h) {
                 size_t e = a;
                 int64_t bytes = 0;
                 while (e < list.size() && bytes < UNIT_BYTES) {
-                    const int64_t b = (int64_t)list[e].ncols * lt.P * (int64_t)fmt_size(list[e].fmt);
+                    const int64_t b = (int64_t)list[e].ncols * slice_bytes(list[e], lt.P);
                     if (e > a && bytes + b > UNIT_BYTES + UNIT_BYTES / 2) break;
                     bytes += b;
                     ++e;
@@ -1131,7 +1200,7 @@ static void build_tasks(hh_handle* h) {
                 ut.po = po;
                 ut.P = lt.P;
                 ut.rb = (int32_t)S.uruns.size();
-                for (int f = 0; f < 4; ++f) {
+                for (int f = 0; f < NFMT; ++f) {
                     for (size_t i = a; i < e; ++i)
                         if (list[i].fmt == f) S.uruns.push_back(list[i]);
                     ut.fe[f] = (int32_t)S.uruns.size();
@@ -1178,20 +1247,37 @@ static void build_tasks(hh_handle* h) {
     }
 }
 
-static bool choose_lowrank_format(const BlockRec& r, double total2, int d, double eps,
-                                  uint32_t mask, int& fmt) {
+// Alg. 3 (eq:amp_prec_choice, evaluated squared: u^2 2^(d l) ||H~_b||^2 <=
+// eps^2 ||H~||^2, ties pass): the lowest precision of the mask that passes,
+// else fp64. With continuum storage (the accessor remark of Sec. 4.3) the
+// candidates are t = 7..23 fraction bits with u = 2^-(t + 1), smallest t first.
+static void choose_lowrank_format(const BlockRec& r, double total2, int d, double eps,
+                                  const hh_options& o, int& fmt, int& t) {
     const double rhs = (eps * eps) * total2;
+    const double lhs = std::ldexp(1.0, d * r.b.level) * r.nb2;
+    t = 0;
+    if (o.continuum) {
+        for (int tt = 7; tt <= 23; ++tt) {
+            const double u = std::ldexp(1.0, -(tt + 1));
+            if ((u * u) * lhs <= rhs) {
+                fmt = HH_FMT_CONT;
+                t = tt;
+                return;
+            }
+        }
+        fmt = HH_FMT_FP64;
+        return;
+    }
     const int order[3] = {HH_FMT_BF16, HH_FMT_FP16, HH_FMT_FP32};
     for (int f : order) {
-        if (!(mask & (1u << f))) continue;
+        if (!(o.precision_mask & (1u << f))) continue;
         const double u = UNIT[f];
-        if (((u * u) * std::ldexp(1.0, d * r.b.level)) * r.nb2 <= rhs) {
+        if ((u * u) * lhs <= rhs) {
             fmt = f;
-            return true;
+            return;
         }
     }
     fmt = HH_FMT_FP64;
-    return true;
 }
 
 static void fill_stats(hh_handle* h, double seconds) {
@@ -1212,13 +1298,14 @@ static void fill_stats(hh_handle* h, double seconds) {
             }
             s.n_blocks_lowrank++;
             s.blocks_by_format[r.fmt]++;
-            s.factor_bytes_by_format[r.fmt] += (int64_t)r.rank * (r.PI + r.PJ) * (int64_t)fmt_size(r.fmt);
+            s.factor_bytes_by_format[r.fmt] +=
+                (int64_t)r.rank * (col_bytes(r.fmt, r.t, r.PI) + col_bytes(r.fmt, r.t, r.PJ));
             s.lowrank_entries += (int64_t)r.rank * (m + n);
             s.total_columns += r.rank;
             s.max_rank = std::max(s.max_rank, r.rank);
-            words += (double)r.rank * (m + n) * BITS[r.fmt] / 64.0;
+            words += (double)r.rank * (m + n) * entry_bits(r.fmt, r.t) / 64.0;
             words64 += (double)r.rank * (m + n);
-            bytes += (double)r.rank * (m + n) * fmt_size(r.fmt);
+            bytes += (double)r.rank * (m + n) * entry_bits(r.fmt, r.t) / 8.0;
         } else {
             s.n_blocks_dense++;
             s.dense_entries += m * n;
@@ -1233,8 +1320,8 @@ static void fill_stats(hh_handle* h, double seconds) {
     for (const auto& r : h->blocks) {
         const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
         if (r.lowrank) {
-            vb += (double)r.rank * n * fmt_size(r.fmt);
-            ub += (double)r.rank * m * fmt_size(r.fmt);
+            vb += (double)r.rank * n * entry_bits(r.fmt, r.t) / 8.0;
+            ub += (double)r.rank * m * entry_bits(r.fmt, r.t) / 8.0;
         } else {
             db += 8.0 * m * n;
         }
@@ -1267,6 +1354,7 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
     if (o.precision_mask == 0) o.precision_mask = 0xF;
     if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
+    if (o.continuum != 0 && o.continuum != 1) fail(HH_EINVAL, "continuum must be 0 or 1");
 
     std::unique_ptr<hh_handle> h(new hh_handle());
     h->plan = make_plan(points, n, d, eta, switch_level, leaf_size);
@@ -1328,13 +1416,14 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
     for (size_t i = 0; i < h->blocks.size(); ++i) {
         BlockRec& r = h->blocks[i];
         if (!r.lowrank) continue;
-        int fmt = HH_FMT_FP64;
-        if (!uniform) choose_lowrank_format(r, total2, d, tol, o.precision_mask, fmt);
+        int fmt = HH_FMT_FP64, t = 0;
+        if (!uniform) choose_lowrank_format(r, total2, d, tol, o, fmt, t);
         r.fmt = fmt;
+        r.t = t;
         if (r.b.kind == HH_BLK_DENSE_NEAR) {
             const int64_t m = r.b.ie - r.b.ib, nn = r.b.je - r.b.jb;
             // keep the neighbour low-rank only when that saves storage
-            if (!((double)r.rank * (m + nn) * BITS[fmt] / 64.0 < (double)(m * nn)))
+            if (!((double)r.rank * (m + nn) * entry_bits(fmt, t) / 64.0 < (double)(m * nn)))
                 to_dense.push_back((int64_t)i);
         }
     }
@@ -1376,6 +1465,7 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     if (o.precision_mask == 0) o.precision_mask = 0xF;
     if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
+    if (o.continuum != 0 && o.continuum != 1) fail(HH_EINVAL, "continuum must be 0 or 1");
     if (!src->all_fp64) fail(HH_ENOTSUP, "hh_derive needs a source whose factors are all fp64");
     for (const auto& r : src->blocks)
         if (r.b.kind == HH_BLK_DENSE_NEAR)
@@ -1415,9 +1505,10 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     for (const auto& r : h->blocks) total2 += r.lowrank ? r.nb2 : r.entry2;
     for (auto& r : h->blocks) {
         if (!r.lowrank) continue;
-        int fmt = HH_FMT_FP64;
-        if (!uniform) choose_lowrank_format(r, total2, h->plan.d, h->tol, o.precision_mask, fmt);
+        int fmt = HH_FMT_FP64, t = 0;
+        if (!uniform) choose_lowrank_format(r, total2, h->plan.d, h->tol, o, fmt, t);
         r.fmt = fmt;
+        r.t = t;
         r.eU = r.eV = 0;
     }
     Builder B(h.get());

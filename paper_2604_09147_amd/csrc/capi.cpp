@@ -107,6 +107,64 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     }
 }
 
+// Workspace of hh_matvec_noalloc: one fixed array per device. Host code never
+// uses the array's name as an address: the device address is looked up once
+// per device with hipGetSymbolAddress (that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[HH_NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+
+static char* scratch_address(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) fail(HH_ENOTSUP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(HH_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
+static int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// The product of product() with the workspace carved from the device's scratch
+// array: gathered x, coefficients, partial rows. Every element the kernels read
+// is written earlier in the same call, so nothing is cleared.
+static void product_noalloc(const hh_handle* h, const void* x, void* y, int64_t nrhs, bool trans,
+                            void* stream) {
+    if (!h) fail(HH_EINVAL, "handle is NULL");
+    if (!x || !y) fail(HH_EINVAL, "x and y must be device pointers");
+    if (x == y) fail(HH_EINVAL, "x and y must not alias");
+    if (nrhs < 1 || nrhs > (1 << 16)) fail(HH_EINVAL, "nrhs must lie in [1, 65536]");
+    check_device(h);
+    const int R = (int)nrhs;
+    const int64_t bx = round256(h->np * R * 8);
+    const int64_t bt = round256(std::max<int64_t>(h->ncols, 1) * R * 8);
+    const int64_t bp = R == 1 ? round256(std::max<int64_t>(h->part_rows, 1) * 8) : 0;
+    if (bx + bt + bp > (int64_t)HH_NOALLOC_SCRATCH_BYTES)
+        fail(HH_ENOTSUP, "the product needs " + std::to_string(bx + bt + bp) +
+                             " bytes of workspace, more than the " +
+                             std::to_string((long long)HH_NOALLOC_SCRATCH_BYTES) +
+                             " of the allocation-free scratch");
+    char* base = scratch_address(h->device);
+    const TaskSet& S = trans ? h->bwd : h->fwd;
+    Desc d = make_desc(h, S, x, y);
+    d.xt = reinterpret_cast<double*>(base);
+    d.tb = reinterpret_cast<double*>(base + bx);
+    d.part = reinterpret_cast<double*>(base + bx + bt);
+    launch_gather(d, nullptr, 1, h->np, R, stream);
+    if (R == 1) {
+        launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
+        launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(), stream);
+    } else {
+        launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, stream);
+        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, stream);
+    }
+    HIPCHK(hipGetLastError());
+}
+
 // Task tables of the last batch (its handles and RHS count) stay on the
 // device; a call with the same batch only uploads the descriptors (x, y and
 // workspace pointers) on its stream. Freeing a member handle drops the plan.
@@ -221,7 +279,8 @@ static void drop_batch_plan(const hh_handle* h) {
 static double block_words(const BlockRec& r) {
     const double m = (double)(r.b.ie - r.b.ib), n = (double)(r.b.je - r.b.jb);
     if (!r.lowrank) return m * n;
-    const double bits = r.fmt == HH_FMT_FP64 ? 64.0 : r.fmt == HH_FMT_FP32 ? 32.0 : 16.0;
+    const double bits = r.fmt == HH_FMT_FP64 ? 64.0 : r.fmt == HH_FMT_FP32 ? 32.0
+                      : r.fmt == HH_FMT_CONT ? 9.0 + r.t : 16.0;
     return (double)r.rank * (m + n) * bits / 64.0;
 }
 
@@ -264,6 +323,17 @@ static int switch_level_search(const double* points, int64_t n, int d, const hh_
     if (s1) std::copy(S1.begin(), S1.end(), s1);
     if (s2) std::copy(S2.begin(), S2.end(), s2);
     return ell;
+}
+
+// Entry i of a continuum column of (9 + t)-bit entries packed back to back
+// (little-endian bit order) from the column's first byte.
+static double decode_cont(const unsigned char* col, int t, int64_t i) {
+    const int w = 9 + t;
+    const int64_t bit = i * w;
+    uint64_t win = 0;
+    for (int b = 0; b < 8; ++b) win |= (uint64_t)col[(bit >> 3) + b] << (8 * b);
+    const uint32_t code = (uint32_t)((win >> (bit & 7)) & ((1ull << w) - 1));
+    return cont_to_f64(code, t);
 }
 
 static double decode(const void* base, int fmt, int64_t i) {
@@ -357,6 +427,13 @@ hh_status hh_matvec_batch(const hh_handle* const* hs, int count, const void* con
     GUARD_END
 }
 
+hh_status hh_matvec_noalloc(const hh_handle* h, const void* x, void* y, int64_t nrhs, int trans,
+                            void* stream) {
+    GUARD_BEGIN
+    product_noalloc(h, x, y, nrhs, trans != 0, stream);
+    GUARD_END
+}
+
 hh_status hh_reserve(hh_handle* h, int64_t max_nrhs) {
     GUARD_BEGIN
     if (!h) fail(HH_EINVAL, "handle is NULL");
@@ -399,6 +476,7 @@ hh_status hh_get_block(const hh_handle* h, int64_t index, hh_block_info* o) {
     o->exp_u = r.eU;
     o->exp_v = r.eV;
     o->lowrank = r.lowrank ? 1 : 0;
+    o->frac_bits = r.lowrank && r.fmt == HH_FMT_CONT ? r.t : 0;
     o->norm2 = r.nb2;
     o->entry_norm2 = r.entry2;
     o->tail_prev = r.tail_prev;
@@ -420,6 +498,18 @@ hh_status hh_get_block_factors(const hh_handle* h, int64_t index, double* U, dou
         HIPCHK(hipMemcpy(D.data(), r.d_ptr, D.size() * 8, hipMemcpyDeviceToHost));
         for (int64_t j = 0; j < n; ++j)
             for (int64_t i = 0; i < m; ++i) U[i + j * m] = D[j * r.PI + h->tpad[r.b.ib + i] - rb];
+    } else if (r.rank > 0 && r.fmt == HH_FMT_CONT) {
+        if (!V) fail(HH_EINVAL, "V is NULL for a low-rank block");
+        const int64_t cu = cont_col_bytes(r.PI, 9 + r.t), cv = cont_col_bytes(r.PJ, 9 + r.t);
+        std::vector<unsigned char> bu((size_t)r.rank * cu + 16, 0), bv((size_t)r.rank * cv + 16, 0);
+        HIPCHK(hipMemcpy(bu.data(), r.u_ptr, (size_t)r.rank * cu, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(bv.data(), r.v_ptr, (size_t)r.rank * cv, hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < r.rank; ++c) {
+            for (int64_t i = 0; i < m; ++i)
+                U[i + c * m] = decode_cont(bu.data() + c * cu, r.t, h->tpad[r.b.ib + i] - rb);
+            for (int64_t j = 0; j < n; ++j)
+                V[j + c * n] = decode_cont(bv.data() + c * cv, r.t, h->tpad[r.b.jb + j] - cb);
+        }
     } else if (r.rank > 0) {
         if (!V) fail(HH_EINVAL, "V is NULL for a low-rank block");
         const size_t es = fmt_size(r.fmt);
@@ -526,6 +616,14 @@ hh_status hh_quantize(const double* in, int64_t n, int format, int e, double* ou
         }
         out[i] = q * b;
     }
+    GUARD_END
+}
+
+hh_status hh_quantize_cont(const double* in, int64_t n, int t, double* out) {
+    GUARD_BEGIN
+    if (n < 0 || (n > 0 && (!in || !out))) fail(HH_EINVAL, "bad arrays");
+    if (t < 7 || t > 23) fail(HH_EINVAL, "fraction bits must lie in [7, 23]");
+    for (int64_t i = 0; i < n; ++i) out[i] = cont_to_f64(f64_to_cont_rne(in[i], t), t);
     GUARD_END
 }
 

@@ -27,7 +27,7 @@ struct TaskSet {                      // one direction of the product
     std::vector<Run> uruns;           // their runs, format-grouped per unit
     std::vector<FinishTask> fin;      // one per nonempty leaf
     std::vector<Run> runs;            // grouped by cluster, clusters in (level, box) order
-    std::vector<int32_t> cl_run;      // 4 (sum_l 2^(d l)) + 1 boundaries (cluster, format)
+    std::vector<int32_t> cl_run;      // NFMT (sum_l 2^(d l)) + 1 boundaries (cluster, format)
     DotTask* d_dot = nullptr;
     DotTask* d_dotm = nullptr;
     LeafTask* d_leaf = nullptr;

@@ -104,10 +104,23 @@ struct PackItem {
     int32_t e;
 };
 
+// Continuum packing: k columns of P fp64 entries (padded-row layout) into k
+// columns of cdw dwords, entries of 9 + t bits back to back.
+struct ContPackItem {
+    const double* src;
+    uint32_t* dst;
+    int64_t P;
+    int64_t cdw;
+    int32_t k;
+    int32_t t;
+};
+
 __host__ __device__ uint16_t f64_to_f16_rne(double x);
 __host__ __device__ uint16_t f64_to_bf16_rne(double x);
 __host__ __device__ double f16_to_f64(uint16_t h);
 __host__ __device__ double bf16_to_f64(uint16_t b);
+__host__ __device__ uint32_t f64_to_cont_rne(double x, int t);
+__host__ __device__ double cont_to_f64(uint32_t code, int t);
 
 void launch_gen(const KernelDev& k, const double* pts, const double* nrm, const int64_t* tpad,
                 const GenItem* items, int nitems, int64_t M, int64_t N, int64_t max_total,
@@ -121,6 +134,7 @@ void launch_finalize(const FinItem* items, int nitems, const int64_t* tpad, hipS
 void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s);
 void launch_pack(const PackItem* items, int nitems, int64_t max_count, hipStream_t s);
 void launch_transpose(const TransItem* items, int nitems, int64_t max_count, hipStream_t s);
+void launch_pack_cont(const ContPackItem* items, int nitems, int64_t max_dwords, hipStream_t s);
 void launch_house_qr(double* A, int64_t ld, int64_t strideA, double* tau, int64_t strideT,
                      int64_t m, int n, int nitems, hipStream_t st);
 void launch_panel_v(const double* A, int64_t ld, int64_t strideA, const double* tau,

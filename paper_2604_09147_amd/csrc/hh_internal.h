@@ -45,6 +45,16 @@ void box_coords(int64_t box, int level, int d, int64_t* c);
 // that a wave lane owning 4 consecutive rows always reads aligned vectors.
 constexpr int ROW_PAD = 4;
 
+// Storage formats of the low-rank factors: HH_FMT_FP64 .. HH_FMT_BF16 and the
+// continuum format HH_FMT_CONT (per block t fraction bits, 9 + t bits per
+// entry, entries packed back to back in every column).
+constexpr int NFMT = 5;
+// Bytes of one continuum column of P entries of w bits: whole 16-byte units,
+// so every column starts 16-byte aligned (constexpr: usable in device code).
+constexpr int64_t cont_col_bytes(int64_t P, int w) {
+    return ((P * w + 127) >> 7) << 4;
+}
+
 struct Run;
 
 // Per-handle device pointers the product kernels need for one direction of the
@@ -57,7 +67,7 @@ struct Desc {
     const void* x;           // caller x (N x R)
     void* y;                 // caller y (N x R)
     const Run* runs;         // runs of every cluster, clusters in (level, box) order
-    const int32_t* cl_run;   // runs of cluster c in format f: [cl_run[4c + f], cl_run[4c + f + 1])
+    const int32_t* cl_run;   // runs of cluster c in format f: [cl_run[NFMT c + f], cl_run[NFMT c + f + 1])
     const Run* uruns;        // runs of the single-vector work units
     double* part;            // partial sums of the work units
     int64_t np;              // padded length
@@ -70,7 +80,8 @@ struct Desc {
 // tb[toff + c] = sum_j col_c[j] xt[xoff + j]  for c < ncols, j < P.
 // The coefficient carries the block's factor scales: tb = 2^exp (col . xt).
 struct DotTask {
-    const void* col0;        // first element of column 0; column c starts c * P later
+    const void* col0;        // first element of column 0; column c starts c * P elements
+                             // later (continuum: c * cont_col_bytes(P, w) bytes later)
     int64_t xoff;            // padded row offset of the slice of xt
     int64_t toff;            // coefficient index of column 0
     int32_t P;               // column length (padded rows, multiple of 4)
@@ -78,7 +89,7 @@ struct DotTask {
     int32_t fmt;             // HH_FMT_*
     int32_t hid;             // handle index in a batched launch
     int32_t exp;             // eU + eV (power-of-two factor scales, exact)
-    int32_t pad_;
+    int32_t w;               // continuum: bits per stored entry (9 + t); else 0
 };
 
 // Columns stored with a common stride and consecutive coefficients, restricted
@@ -93,7 +104,7 @@ struct Run {
     int32_t stride;          // elements between consecutive columns
     int32_t toff;
     int32_t ncols;
-    int16_t pad_;
+    int16_t w;               // continuum: bits per stored entry (9 + t); else 0
     int8_t fmt;              // HH_FMT_*; dense blocks are HH_FMT_FP64
     int8_t from_x;
 };
@@ -109,16 +120,16 @@ struct LeafTask {
 
 // A slice of one leaf's runs (one wave of the single-vector accumulation).
 // Its runs in the unit run list are grouped by format: fp64 [rb, fe[0]),
-// fp32 [fe[0], fe[1]), fp16 [fe[1], fe[2]), bf16 [fe[2], fe[3]). The wave
-// writes its partial sum of the leaf's rows to part[po .. po + P).
+// fp32 [fe[0], fe[1]), fp16 [fe[1], fe[2]), bf16 [fe[2], fe[3]), continuum
+// [fe[3], fe[4]). The wave writes its partial sum of the leaf's rows to
+// part[po .. po + P).
 struct UnitTask {
     int64_t poff;            // padded offset of the leaf
     int64_t po;              // offset of the unit's partial rows
     int32_t P;               // padded rows of the leaf
     int32_t rb;
-    int32_t fe[4];
+    int32_t fe[NFMT];
     int32_t hid;             // handle index in a batched launch
-    int32_t pad_;
 };
 
 // One leaf of the finishing kernel: y rows = sum over its nu units of
@@ -136,6 +147,7 @@ struct FinishTask {
 struct BlockRec {
     Blk b;
     int32_t rank = 0, fmt = HH_FMT_FP64, eU = 0, eV = 0;
+    int32_t t = 0;                    // fraction bits when fmt == HH_FMT_CONT
     bool lowrank = false;
     double nb2 = 0, entry2 = 0, tail_prev = 0, tail = 0;
     const void* u_ptr = nullptr;      // stored factors (format fmt), padded-row layout

@@ -64,6 +64,37 @@ __host__ __device__ uint16_t f64_to_bf16_rne(double x) {
     return sign | (uint16_t)out;
 }
 
+// Continuum storage: t fraction bits (7 <= t <= 23) behind an 8-bit exponent
+// with the exponent range of fp32 (gradual underflow below 2^-126), sign
+// first: a (9 + t)-bit code equal to the top 9 + t bits of the fp32 encoding of
+// the rounded value (every such value is an fp32 number). t = 7 is bf16.
+__host__ __device__ uint32_t f64_to_cont_rne(double x, int t) {
+    const uint64_t bits = __builtin_bit_cast(uint64_t, x);
+    const uint32_t sign = (uint32_t)(bits >> 63) << (8 + t);
+    const uint32_t inf = 0xFFu << t;
+    int ex = (int)((bits >> 52) & 0x7FF);
+    uint64_t man = bits & ((1ull << 52) - 1);
+    if (ex == 0x7FF) return sign | inf | (man ? (1u << (t - 1)) : 0u);
+    if (ex == 0) return sign;
+    int e = ex - 1023;
+    if (e > 127) return sign | inf;
+    uint64_t M = man | (1ull << 52);
+    int ue = (e > -126 ? e : -126) - t;             // exponent of the ulp at |x|
+    int shift = 52 + ue - e;                        // >= 29
+    if (shift >= 64) return sign;
+    uint64_t q = M >> shift;
+    uint64_t rem = M & ((1ull << shift) - 1);
+    uint64_t half = 1ull << (shift - 1);
+    if (rem > half || (rem == half && (q & 1))) ++q;
+    uint32_t out = e >= -126 ? ((uint32_t)(e + 127) << t) + (uint32_t)q - (1u << t) : (uint32_t)q;
+    if (out >= inf) out = inf;
+    return sign | out;
+}
+
+__host__ __device__ double cont_to_f64(uint32_t code, int t) {
+    return (double)__builtin_bit_cast(float, code << (23 - t));
+}
+
 __host__ __device__ double f16_to_f64(uint16_t h) {
     int ex = (h >> 10) & 0x1F, man = h & 0x3FF;
     double v;
@@ -710,6 +741,27 @@ __global__ void pack_kernel(const PackItem* items) {
     }
 }
 
+// One thread per output dword: the entries overlapping bits [32 j, 32 j + 32)
+// of column c, each rounded to t fraction bits (entries past P are zero).
+__global__ void pack_cont_kernel(const ContPackItem* items) {
+    const ContPackItem it = items[blockIdx.y];
+    const int w = 9 + it.t;
+    const int64_t total = (int64_t)it.k * it.cdw;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = q / it.cdw, j = q - c * it.cdw;
+        const int64_t b0 = 32 * j;
+        const int64_t i0 = b0 / w, i1 = (b0 + 31) / w;
+        uint64_t acc = 0;
+        for (int64_t i = i0; i <= i1 && i < it.P; ++i) {
+            const uint64_t code = f64_to_cont_rne(it.src[c * it.P + i], it.t);
+            const int64_t sh = i * w - b0;
+            acc |= sh >= 0 ? (code << sh) : (code >> (-sh));
+        }
+        it.dst[q] = (uint32_t)acc;
+    }
+}
+
 // One item per blockIdx.y; element (i, j) of src goes to (j, i) of dst.
 __global__ void transpose_kernel(const TransItem* items) {
     const TransItem it = items[blockIdx.y];
@@ -781,6 +833,11 @@ void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s)
 void launch_transpose(const TransItem* items, int nitems, int64_t max_count, hipStream_t s) {
     dim3 grid(grid_for(max_count, 4096), nitems);
     hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, items);
+}
+
+void launch_pack_cont(const ContPackItem* items, int nitems, int64_t max_dwords, hipStream_t s) {
+    dim3 grid(grid_for(max_dwords, 2048), nitems);
+    hipLaunchKernelGGL(pack_cont_kernel, grid, dim3(256), 0, s, items);
 }
 
 void launch_pack(const PackItem* items, int nitems, int64_t max_count, hipStream_t s) {

@@ -158,6 +158,82 @@ __device__ inline double wave_sum(double v) {
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// ------------------------------------------------------ continuum storage
+// A continuum column holds its entries back to back, W = 9 + t bits each, in
+// little-endian bit order (entry i at bits [i W, i W + W) of the column); an
+// entry is the top W bits of the fp32 encoding of its value. Columns start at
+// 16-byte boundaries (cont_col_bytes). A lane owning 4 consecutive entries
+// loads the 4 dwords that hold them (5 when W > 24) from the dword holding
+// the first one, shifts the words down by the first entry's bit offset in that
+// dword (a per-lane funnel shift), after which entry j sits at bit j W for
+// every lane: extracting it is one more funnel shift by a compile-time amount
+// and a left shift that drops the next entry's bits. The values are exact fp32
+// numbers, widened exactly to fp64.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+template <int W>
+struct CRaw { uint32_t d[W > 24 ? 5 : 4]; };
+
+// Byte offset of the dword holding entry `row` of a column, and the entry's
+// bit offset inside it.
+template <int W>
+__device__ inline void cpos(int64_t row, uint32_t& off, uint32_t& sh) {
+    const uint64_t bit = (uint64_t)row * W;
+    off = (uint32_t)(bit >> 5) << 2;
+    sh = (uint32_t)bit & 31u;
+}
+
+template <int W>
+__device__ inline CRaw<W> cload(rsrc_t rs, uint32_t off) {
+    CRaw<W> r;
+    const u32x4_t v = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z; r.d[3] = v.w;
+    if constexpr (W > 24) r.d[4] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 16, 0, 0);
+    return r;
+}
+
+template <int W>
+__device__ inline void cwiden(const CRaw<W>& r, uint32_t sh, double v[4]) {
+    uint32_t e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t hi = 0u;
+        if constexpr (W > 24) hi = r.d[k + 1];
+        else if (k < 3) hi = r.d[k + 1];
+        e[k] = __builtin_amdgcn_alignbit(hi, r.d[k], sh);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int pos = j * W, k = pos >> 5, s = pos & 31;
+        const uint32_t win = s == 0 ? e[k] : __builtin_amdgcn_alignbit(e[k + 1 < 4 ? k + 1 : 3], e[k], s);
+        v[j] = (double)__uint_as_float(win << (32 - W));
+    }
+}
+
+// Calls F.template operator()<W>() for the run-time width w (16..32).
+template <class F>
+__device__ inline void with_width(int w, F&& f) {
+    switch (w) {
+        case 16: f.template operator()<16>(); break;
+        case 17: f.template operator()<17>(); break;
+        case 18: f.template operator()<18>(); break;
+        case 19: f.template operator()<19>(); break;
+        case 20: f.template operator()<20>(); break;
+        case 21: f.template operator()<21>(); break;
+        case 22: f.template operator()<22>(); break;
+        case 23: f.template operator()<23>(); break;
+        case 24: f.template operator()<24>(); break;
+        case 25: f.template operator()<25>(); break;
+        case 26: f.template operator()<26>(); break;
+        case 27: f.template operator()<27>(); break;
+        case 28: f.template operator()<28>(); break;
+        case 29: f.template operator()<29>(); break;
+        case 30: f.template operator()<30>(); break;
+        case 31: f.template operator()<31>(); break;
+        default: f.template operator()<32>(); break;
+    }
+}
+
 // ------------------------------------------------------------------ gather
 __global__ void gather_kernel(Desc d, const Desc* descs, int R) {
     const Desc D = descs ? ldrec<Desc>(descs + blockIdx.y) : d;
@@ -247,6 +323,80 @@ __device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs,
     else dot_r1<FMT, R8, NU>(t, xg, xs, lds, tb, wave, lane);
 }
 
+// Continuum columns: UC columns x UR pieces of 256 rows per wave iteration,
+// fp64 accumulation, the per-lane bit position computed once per piece.
+template <int W, int UR>
+__device__ void dot_cont(const DotTask& t, const double* xg, const double* xs, bool lds,
+                         double* tb, int wave, int lane) {
+    constexpr int UC = 8 / UR;
+    const int P = t.P;
+    const uint32_t cb = (uint32_t)cont_col_bytes(P, W);
+    const rsrc_t rs = make_rsrc(t.col0, (int64_t)t.ncols * cb);
+    for (int c0 = wave * UC; c0 < t.ncols; c0 += 4 * UC) {
+        double a[UC];
+#pragma unroll
+        for (int u = 0; u < UC; ++u) a[u] = 0.0;
+        for (int rb = 0; rb < P; rb += 256 * UR) {
+            CRaw<W> raw[UC][UR];
+            uint32_t sh[UR];
+#pragma unroll
+            for (int ur = 0; ur < UR; ++ur) {
+                const int r = rb + 256 * ur + 4 * lane;
+                uint32_t off;
+                cpos<W>(r < P ? r : 0, off, sh[ur]);
+#pragma unroll
+                for (int uc = 0; uc < UC; ++uc) {
+                    const int c = c0 + uc < t.ncols ? c0 + uc : t.ncols - 1;
+                    raw[uc][ur] = cload<W>(rs, off + (uint32_t)c * cb);
+                }
+            }
+#pragma unroll
+            for (int ur = 0; ur < UR; ++ur) {
+                const int r = rb + 256 * ur + 4 * lane;
+                double xv[4] = {0.0, 0.0, 0.0, 0.0};
+                if (r < P) {
+                    if (lds) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) xv[q] = xs[r + q];
+                    } else {
+                        const dbl2_t x0 = ldg<dbl2_t>(xg + r), x1 = ldg<dbl2_t>(xg + r + 2);
+                        xv[0] = x0.x; xv[1] = x0.y; xv[2] = x1.x; xv[3] = x1.y;
+                    }
+                }
+#pragma unroll
+                for (int uc = 0; uc < UC; ++uc) {
+                    double v[4];
+                    cwiden<W>(raw[uc][ur], sh[ur], v);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) a[uc] = fma(v[q], xv[q], a[uc]);
+                }
+            }
+        }
+#pragma unroll
+        for (int uc = 0; uc < UC; ++uc) {
+            const double s = ldexp(wave_sum(a[uc]), t.exp);
+            if (lane == 0 && c0 + uc < t.ncols) stg<double>(tb + t.toff + c0 + uc, s);
+        }
+    }
+}
+
+struct DotCont {
+    const DotTask& t;
+    const double* xg;
+    const double* xs;
+    bool lds;
+    double* tb;
+    int wave, lane;
+    template <int W>
+    __device__ void operator()() const {
+        const int nb = (t.P + 255) / 256;
+        if (!lds && nb > 1) dot_cont<W, 2>(t, xg, xs, lds, tb, wave, lane);
+        else if (nb <= 1) dot_cont<W, 1>(t, xg, xs, lds, tb, wave, lane);
+        else if (nb <= 2) dot_cont<W, 2>(t, xg, xs, lds, tb, wave, lane);
+        else dot_cont<W, 4>(t, xg, xs, lds, tb, wave, lane);
+    }
+};
+
 template <int NU, int XL>
 __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks) {
     __shared__ double xs[XL];
@@ -263,7 +413,8 @@ __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks
         case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane); break;
         case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32, NU>(t, x, xs, lds, D.tb, wave, lane); break;
         case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-        default: dot_r1_any<HH_FMT_BF16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+        case HH_FMT_BF16: dot_r1_any<HH_FMT_BF16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+        default: with_width(t.w, DotCont{t, x, xs, lds, D.tb, wave, lane}); break;
     }
 }
 
@@ -437,6 +588,80 @@ __device__ inline void unit_runs_fmt(const Desc& D, const UnitTask& ut, int b, i
     }
 }
 
+// One continuum run on a lane's 4 rows: columns in batches of 8 (SPLIT: the
+// wave's groups take every G-th column), then clamped batches of 4.
+template <int W, bool SPLIT>
+__device__ inline void apply_run_cont(const Run& rn, rsrc_t rs, uint32_t off, uint32_t sh,
+                                      const double* coef, int g, int G, double acc[4][1]) {
+    const uint32_t cb = (uint32_t)rn.stride * 4u;        // continuum stride is in dwords
+    const int n = rn.ncols;
+    const int step = SPLIT ? G : 1;
+    int c = SPLIT ? g : 0;
+    constexpr int U = 8;
+    for (; c + (U - 1) * step < n; c += U * step) {
+        CRaw<W> raw[U];
+        double cf[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int cc = c + u * step;
+            raw[u] = cload<W>(rs, off + (uint32_t)cc * cb);
+            cf[u] = SPLIT ? ldg<double>(coef + rn.toff + cc) : ldc<double>(coef + rn.toff + cc);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double v[4];
+            cwiden<W>(raw[u], sh, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][0] = fma(v[q], cf[u], acc[q][0]);
+        }
+    }
+    for (; c < n; c += 4 * step) {
+        CRaw<W> raw[4];
+        double cf[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int cu = c + u * step;
+            const int cc = cu < n ? cu : n - 1;
+            raw[u] = cload<W>(rs, off + (uint32_t)cc * cb);
+            const double w = SPLIT ? ldg<double>(coef + rn.toff + cc) : ldc<double>(coef + rn.toff + cc);
+            cf[u] = cu < n ? w : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double v[4];
+            cwiden<W>(raw[u], sh, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][0] = fma(v[q], cf[u], acc[q][0]);
+        }
+    }
+}
+
+template <bool SPLIT>
+struct RunCont {
+    const Run& rn;
+    rsrc_t rs;
+    int64_t crow;            // first row of the lane inside the cluster's columns
+    const double* coef;
+    int g, G;
+    double (*acc)[1];
+    template <int W>
+    __device__ void operator()() const {
+        uint32_t off, sh;
+        cpos<W>(crow, off, sh);
+        apply_run_cont<W, SPLIT>(rn, rs, off, sh, coef, g, G, acc);
+    }
+};
+
+template <bool SPLIT>
+__device__ inline void unit_runs_cont(const Desc& D, const UnitTask& ut, int b, int e, int64_t row,
+                                      int g, int G, double acc[4][1]) {
+    for (int i = b; i < e; ++i) {
+        const Run rn = ldrec<Run>(D.uruns + i);
+        const rsrc_t rs = make_rsrc(rn.base, (int64_t)rn.ncols * rn.stride * 4);
+        with_width(rn.w, RunCont<SPLIT>{rn, rs, ut.poff - rn.pc + row, D.tb, g, G, acc});
+    }
+}
+
 template <bool SPLIT, int UB>
 __device__ inline void unit_runs(const Desc& D, const UnitTask& ut, int64_t row, int g, int G,
                                  double acc[4][1], bool pipe) {
@@ -444,6 +669,7 @@ __device__ inline void unit_runs(const Desc& D, const UnitTask& ut, int64_t row,
     unit_runs_fmt<HH_FMT_FP32, SPLIT, UB>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc, pipe);
     unit_runs_fmt<HH_FMT_FP16, SPLIT, UB>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc, pipe);
     unit_runs_fmt<HH_FMT_BF16, SPLIT, UB>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc, pipe);
+    if (ut.fe[4] > ut.fe[3]) unit_runs_cont<SPLIT>(D, ut, ut.fe[3], ut.fe[4], row, g, G, acc);
 }
 
 // Four units per workgroup, one per wave; the waves never synchronise.
@@ -455,11 +681,16 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
     const UnitTask ut = ldrec<UnitTask>(units + ui);
     const Desc D = descs ? ldrec<Desc>(descs + ut.hid) : d;
     const int P = ut.P;
-    int lps = 1;
-    while (lps < 64 && 4 * lps < P) lps <<= 1;
-    const int G = 64 / lps, g = lane / lps, sl = lane % lps;
-    const int strip = 4 * lps;
-    for (int jlo = 0; jlo < P; jlo += strip) {
+    // strips of 256 rows, then one strip for the remaining rows sized to them:
+    // lps lanes per 4-row group cover them, and the 64 / lps groups of the wave
+    // share out the columns, so a leaf a little above 256 rows does not pay a
+    // second full pass over its runs for a few rows
+    for (int jlo = 0; jlo < P;) {
+        const int rem = P - jlo;
+        int lps = 1;
+        while (lps < 64 && 4 * lps < rem) lps <<= 1;
+        const int G = 64 / lps, g = lane / lps, sl = lane % lps;
+        const int strip = 4 * lps;
         const int prow = jlo + 4 * sl;
         const int64_t row = prow < P ? prow : 0;     // clamped: in bounds, never written
         double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
@@ -472,6 +703,7 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (prow + q < P) stg<double>(D.part + ut.po + prow + q, acc[q][0]);
+        jlo += strip;
     }
 }
 
@@ -603,6 +835,81 @@ __device__ void dotm_tile(const DotTask& t, const Desc& D, int R, int g, int lan
             }
 }
 
+// The same tile over continuum columns (exponent sum 0): lane (i, k) decodes
+// rows p .. p + 3 of column i of each column tile.
+template <int W, int NT, int MT>
+__device__ void dotm_tile_cont(const DotTask& t, const Desc& D, int R, int g, int lane) {
+    const int i = lane & 15, kq = lane >> 4;
+    const int P = t.P;
+    const int64_t cb = cont_col_bytes(P, W);
+    rsrc_t rs[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int c = 16 * mt + i < t.ncols ? 16 * mt + i : t.ncols - 1;
+        rs[mt] = make_rsrc(static_cast<const char*>(t.col0) + (int64_t)c * cb, cb);
+    }
+    const double* xb = D.xt + t.xoff * (int64_t)R;
+    int rr[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int r = 16 * (g * NT + u) + i;
+        rr[u] = r < R ? r : R - 1;
+    }
+    constexpr int AC = NT * MT >= 4 ? 1 : 4 / (NT * MT);
+    dbl4_t acc[AC][MT][NT];
+#pragma unroll
+    for (int h = 0; h < AC; ++h)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[h][mt][u] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+    for (int p0 = 0; p0 < P; p0 += 16) {
+        const int p = p0 + 4 * kq;
+        const bool pok = p < P;
+        uint32_t off, sh;
+        cpos<W>(pok ? p : 0, off, sh);
+        double a[MT][4];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) cwiden<W>(cload<W>(rs[mt], off), sh, a[mt]);
+        double b[4][NT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) b[m][u] = ldg<double>(xb + (int64_t)(pok ? p + m : 0) * R + rr[u]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const double am = pok ? a[mt][m] : 0.0;
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    acc[m % AC][mt][u] = mfma16(am, b[m][u], acc[m % AC][mt][u]);
+            }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = acc[0][mt][u][r];
+#pragma unroll
+                for (int h = 1; h < AC; ++h) v += acc[h][mt][u][r];
+                const int cm = 16 * mt + 4 * r + kq, rhs = 16 * (g * NT + u) + i;
+                if (cm < t.ncols && rhs < R)
+                    stg<double>(D.tb + (t.toff + cm) * (int64_t)R + rhs, ldexp(v, t.exp));
+            }
+}
+
+template <int NT>
+struct DotmCont {
+    const DotTask& t;
+    const Desc& D;
+    int R, g, lane;
+    template <int W>
+    __device__ void operator()() const { dotm_tile_cont<W, NT, DOTM_MT>(t, D, R, g, lane); }
+};
+
 // Tiles x right-hand-side groups, four per workgroup (one per wave); the groups
 // of one tile are neighbours, so its columns are read from HBM about once.
 template <int NT>
@@ -619,7 +926,8 @@ __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, co
         case HH_FMT_FP64: dotm_tile<HH_FMT_FP64, NT, DOTM_MT>(t, D, R, g, lane); break;
         case HH_FMT_FP32: dotm_tile<HH_FMT_FP32, NT, DOTM_MT>(t, D, R, g, lane); break;
         case HH_FMT_FP16: dotm_tile<HH_FMT_FP16, NT, DOTM_MT>(t, D, R, g, lane); break;
-        default: dotm_tile<HH_FMT_BF16, NT, DOTM_MT>(t, D, R, g, lane); break;
+        case HH_FMT_BF16: dotm_tile<HH_FMT_BF16, NT, DOTM_MT>(t, D, R, g, lane); break;
+        default: with_width(t.w, DotmCont<NT>{t, D, R, g, lane}); break;
     }
 }
 
@@ -639,7 +947,7 @@ __device__ inline void accm_runs(const Desc& D, int64_t ci, const LeafTask& lt, 
         const int r = 16 * (g * NT + u) + i;
         rr[u] = r < R ? r : R - 1;
     }
-    const int rb = ldc<int32_t>(D.cl_run + 4 * ci + F), re = ldc<int32_t>(D.cl_run + 4 * ci + F + 1);
+    const int rb = ldc<int32_t>(D.cl_run + NFMT * ci + F), re = ldc<int32_t>(D.cl_run + NFMT * ci + F + 1);
     for (int ri = rb; ri < re; ++ri) {
         const Run rn = ldrec<Run>(D.runs + ri);
         const double* coef = rn.from_x ? D.xt : D.tb;
@@ -670,6 +978,69 @@ __device__ inline void accm_runs(const Desc& D, int64_t ci, const LeafTask& lt, 
     }
 }
 
+// The same for the cluster's continuum runs (the width W is per run).
+template <int W, int NT>
+__device__ inline void accm_run_cont(const Run& rn, const double* tb, int64_t crow, int R, int g,
+                                     int lane, dbl4_t acc[4][NT]) {
+    const int i = lane & 15, kq = lane >> 4;
+    int rr[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int r = 16 * (g * NT + u) + i;
+        rr[u] = r < R ? r : R - 1;
+    }
+    const uint32_t cb = (uint32_t)rn.stride * 4u;
+    const rsrc_t rs = make_rsrc(rn.base, (int64_t)rn.ncols * cb);
+    uint32_t off, sh;
+    cpos<W>(crow, off, sh);
+    const int n = rn.ncols;
+    constexpr int KS = NT >= 4 ? 2 : 4;
+    for (int c = 0; c < n; c += 4 * KS) {
+        double a[KS][4];
+        double b[KS][NT];
+#pragma unroll
+        for (int s4 = 0; s4 < KS; ++s4) {
+            const int cc = c + 4 * s4 + kq;
+            const int ccl = cc < n ? cc : n - 1;
+            cwiden<W>(cload<W>(rs, off + (uint32_t)ccl * cb), sh, a[s4]);
+            if (cc >= n) a[s4][0] = a[s4][1] = a[s4][2] = a[s4][3] = 0.0;
+#pragma unroll
+            for (int u = 0; u < NT; ++u) b[s4][u] = ldg<double>(tb + ((int64_t)rn.toff + ccl) * R + rr[u]);
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < KS; ++s4)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < NT; ++u) acc[q][u] = mfma16(a[s4][q], b[s4][u], acc[q][u]);
+    }
+}
+
+template <int NT>
+struct AccmCont {
+    const Run& rn;
+    const double* tb;
+    int64_t crow;
+    int R, g, lane;
+    dbl4_t (*acc)[NT];
+    template <int W>
+    __device__ void operator()() const { accm_run_cont<W, NT>(rn, tb, crow, R, g, lane, acc); }
+};
+
+template <int NT>
+__device__ inline void accm_runs_cont(const Desc& D, int64_t ci, const LeafTask& lt, int rowbase,
+                                      int R, int g, int lane, dbl4_t acc[4][NT]) {
+    const int i = lane & 15;
+    const int row0 = rowbase + 4 * i;
+    const int rb = ldc<int32_t>(D.cl_run + NFMT * ci + HH_FMT_CONT);
+    const int re = ldc<int32_t>(D.cl_run + NFMT * ci + HH_FMT_CONT + 1);
+    for (int ri = rb; ri < re; ++ri) {
+        const Run rn = ldrec<Run>(D.runs + ri);
+        const int64_t crow = lt.poff - rn.pc + (row0 < lt.P ? row0 : 0);
+        with_width(rn.w, AccmCont<NT>{rn, D.tb, crow, R, g, lane, acc});
+    }
+}
+
 // One workgroup per (leaf, right-hand-side group); wave w owns rows 64 w ..
 // 64 w + 63 of each 256-row strip of the leaf; writes y in caller order.
 template <int NT>
@@ -695,6 +1066,7 @@ __global__ __launch_bounds__(256) void accm_kernel(Desc d, const Desc* descs, co
             accm_runs<HH_FMT_FP32, NT>(D, ci, lt, rowbase, R, g, lane, acc);
             accm_runs<HH_FMT_FP16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
             accm_runs<HH_FMT_BF16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
+            accm_runs_cont<NT>(D, ci, lt, rowbase, R, g, lane, acc);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)

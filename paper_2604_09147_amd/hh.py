@@ -16,16 +16,17 @@ LIB_PATH = os.path.join(_HERE, "lib", "libhhmat.so")
 
 HH_OK, HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENOTSUP, HH_EINTERNAL = range(6)
 LOG, INV_R, INV_R2, GAUSS, MATERN, DOUBLE_LAYER = 1, 2, 3, 4, 5, 6
-FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16 = 0, 1, 2, 3
+FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16, FMT_CONT = 0, 1, 2, 3, 4
 IO_F64, IO_F32 = 0, 1
 BLK_FAR, BLK_NEAR, BLK_WEAK, BLK_DIAG, BLK_DENSE_NEAR = range(5)
 
 # Exported functions, in the order include/hh.h declares them.
 EXPORTS = ["hh_build", "hh_derive", "hh_switch_level_search", "hh_matvec", "hh_matvec_t",
-           "hh_matvec_timed", "hh_matvec_batch", "hh_reserve",
+           "hh_matvec_timed", "hh_matvec_batch", "hh_matvec_noalloc", "hh_reserve",
            "hh_get_stats", "hh_block_count", "hh_get_block", "hh_get_block_factors",
            "hh_get_perm", "hh_io_dtype", "hh_size", "hh_free", "hh_plan_create", "hh_plan_info",
-           "hh_plan_blocks", "hh_plan_perm", "hh_plan_free", "hh_quantize", "hh_last_error"]
+           "hh_plan_blocks", "hh_plan_perm", "hh_plan_free", "hh_quantize", "hh_quantize_cont",
+           "hh_last_error"]
 
 
 class HHError(RuntimeError):
@@ -41,15 +42,15 @@ class Kernel(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision_mask", C.c_uint32), ("uniform_fp64", C.c_int), ("io_dtype", C.c_int),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("continuum", C.c_int)]
 
 
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int32), ("d", C.c_int32), ("L", C.c_int32), ("ell", C.c_int32),
                 ("leaf_size", C.c_int32), ("max_rank", C.c_int32),
                 ("n_blocks_lowrank", C.c_int64), ("n_blocks_rank0", C.c_int64),
-                ("n_blocks_dense", C.c_int64), ("blocks_by_format", C.c_int64 * 4),
-                ("factor_bytes_by_format", C.c_int64 * 4), ("dense_bytes", C.c_int64),
+                ("n_blocks_dense", C.c_int64), ("blocks_by_format", C.c_int64 * 5),
+                ("factor_bytes_by_format", C.c_int64 * 5), ("dense_bytes", C.c_int64),
                 ("lowrank_entries", C.c_int64), ("dense_entries", C.c_int64),
                 ("total_columns", C.c_int64), ("storage_words", C.c_double),
                 ("storage_words_fp64", C.c_double), ("matvec_bytes", C.c_double),
@@ -69,7 +70,8 @@ class BlockInfo(C.Structure):
                 ("format", C.c_int32), ("box_i", C.c_int64), ("box_j", C.c_int64),
                 ("row_begin", C.c_int64), ("row_end", C.c_int64), ("col_begin", C.c_int64),
                 ("col_end", C.c_int64), ("exp_u", C.c_int32), ("exp_v", C.c_int32),
-                ("lowrank", C.c_int32), ("norm2", C.c_double), ("entry_norm2", C.c_double),
+                ("lowrank", C.c_int32), ("frac_bits", C.c_int32), ("norm2", C.c_double),
+                ("entry_norm2", C.c_double),
                 ("tail_prev", C.c_double), ("tail", C.c_double)]
 
 
@@ -101,6 +103,7 @@ def lib() -> C.CDLL:
         "hh_matvec_timed": ([_P, _P, _P, C.c_int64, _P, C.c_int, _DP], C.c_int),
         "hh_matvec_batch": ([C.POINTER(_P), C.c_int, C.POINTER(_P), C.POINTER(_P), C.c_int64, _P],
                             C.c_int),
+        "hh_matvec_noalloc": ([_P, _P, _P, C.c_int64, C.c_int, _P], C.c_int),
         "hh_reserve": ([_P, C.c_int64], C.c_int),
         "hh_get_stats": ([_P, C.POINTER(Stats)], C.c_int),
         "hh_block_count": ([_P, _I64P], C.c_int),
@@ -117,6 +120,7 @@ def lib() -> C.CDLL:
         "hh_plan_perm": ([_P, _I64P], C.c_int),
         "hh_plan_free": ([_P], None),
         "hh_quantize": ([_DP, C.c_int64, C.c_int, C.c_int, _DP], C.c_int),
+        "hh_quantize_cont": ([_DP, C.c_int64, C.c_int, _DP], C.c_int),
         "hh_last_error": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -170,6 +174,14 @@ def plan(points, eta: float, switch_level: int, leaf_size: int) -> dict:
         lib().hh_plan_free(h)
 
 
+def quantize_cont(values, t: int) -> np.ndarray:
+    """The library's continuum rounding (t fraction bits, RNE from float64)."""
+    v = np.ascontiguousarray(values, dtype=np.float64).ravel()
+    out = np.empty_like(v)
+    _check(lib().hh_quantize_cont(_dptr(v), v.size, int(t), _dptr(out)))
+    return out.reshape(np.shape(values))
+
+
 def quantize(values, fmt: int, e: int = 0) -> np.ndarray:
     """The library's storage rounding (RNE from float64, scale 2^-e), decoded."""
     v = np.ascontiguousarray(values, dtype=np.float64).ravel()
@@ -179,7 +191,7 @@ def quantize(values, fmt: int, e: int = 0) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ handles
-def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, seed):
+def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, seed, continuum=False):
     """hh_kernel and hh_options structs (and the normals array they point to)."""
     nrm = None
     k = Kernel(int(kernel), float(scale), float(h), None)
@@ -187,7 +199,7 @@ def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, see
         nrm = np.ascontiguousarray(normals, dtype=np.float64)
         k.normals = _dptr(nrm)
     o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io_dtype == "f32" else IO_F64,
-                int(seed))
+                int(seed), int(bool(continuum)))
     return k, o, nrm
 
 
@@ -221,10 +233,20 @@ def _torch_context() -> None:
     if torch.cuda.is_available():
         torch.cuda.init()
 
-def _stream_ptr(stream=None):
+def _stream_ptr(stream=None, tensors=()):
+    """Raw handle of the stream the library launches on. For a stream other
+    than the current one, that stream first waits for the current stream (which
+    produced the inputs and any contiguous copy of them) and the tensors are
+    recorded as in use on it, so the caching allocator does not hand their
+    memory out before the library's kernels have read or written it."""
     import torch
-    s = torch.cuda.current_stream() if stream is None else stream
-    return C.c_void_p(s.cuda_stream)
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        return C.c_void_p(cur.cuda_stream)
+    stream.wait_stream(cur)
+    for t in tensors:
+        t.record_stream(stream)
+    return C.c_void_p(stream.cuda_stream)
 
 
 class HMatrix:
@@ -233,7 +255,7 @@ class HMatrix:
     def __init__(self, points, kernel: int, tol: float, eta: float, switch_level: int,
                  leaf_size: int, scale: float = 1.0, h: float = 1.0, normals=None,
                  mask: int = 0xF, uniform_fp64: bool = False, io_dtype: str = "f64",
-                 seed: int = 0, _handle=None):
+                 seed: int = 0, continuum: bool = False, _handle=None):
         self._h = None
         if _handle is not None:
             self._h = _handle
@@ -241,7 +263,7 @@ class HMatrix:
             pts = np.ascontiguousarray(points, dtype=np.float64)
             n, d = pts.shape
             k, o, self._normals = _kernel_options(kernel, scale, h, normals, mask, uniform_fp64,
-                                                  io_dtype, seed)
+                                                  io_dtype, seed, continuum)
             _torch_context()
             hp = _P()
             _check(lib().hh_build(_dptr(pts), n, d, C.byref(k), float(tol), float(eta),
@@ -271,14 +293,14 @@ class HMatrix:
         """y = H^ x on the current stream (Alg. 4)."""
         xc, y, nrhs = self._prep(x, out)
         _check(lib().hh_matvec(self._h, C.c_void_p(xc.data_ptr()), C.c_void_p(y.data_ptr()),
-                               nrhs, _stream_ptr(stream)))
+                               nrhs, _stream_ptr(stream, (xc, y))))
         return y
 
     def matvec_t(self, x, out=None, stream=None):
         """y = H^^T x on the current stream."""
         xc, y, nrhs = self._prep(x, out)
         _check(lib().hh_matvec_t(self._h, C.c_void_p(xc.data_ptr()), C.c_void_p(y.data_ptr()),
-                                 nrhs, _stream_ptr(stream)))
+                                 nrhs, _stream_ptr(stream, (xc, y))))
         return y
 
     def matvec_timed(self, x, out=None, stream=None, trans=False):
@@ -286,16 +308,17 @@ class HMatrix:
         xc, y, nrhs = self._prep(x, out)
         ms = np.zeros(3)
         _check(lib().hh_matvec_timed(self._h, C.c_void_p(xc.data_ptr()), C.c_void_p(y.data_ptr()),
-                                     nrhs, _stream_ptr(stream), int(bool(trans)), _dptr(ms)))
+                                     nrhs, _stream_ptr(stream, (xc, y)), int(bool(trans)), _dptr(ms)))
         return y, ms
 
     def reserve(self, max_nrhs: int) -> None:
         _check(lib().hh_reserve(self._h, int(max_nrhs)))
 
     def derive(self, mask: int = 0xF, uniform_fp64: bool = False, io_dtype: str | None = None,
-               seed: int = 0) -> "HMatrix":
+               seed: int = 0, continuum: bool = False) -> "HMatrix":
         io = self.io_dtype if io_dtype is None else io_dtype
-        o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io == "f32" else IO_F64, int(seed))
+        o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io == "f32" else IO_F64, int(seed),
+                    int(bool(continuum)))
         hp = _P()
         _check(lib().hh_derive(self._h, C.byref(o), C.byref(hp)))
         return HMatrix(None, 0, 0, 0, 0, 0, _handle=hp)
@@ -372,5 +395,5 @@ def matvec_batch(mats, xs, ys=None, stream=None):
     hs = (_P * count)(*[m._h for m in mats])
     xp = (_P * count)(*[C.c_void_p(x.data_ptr()) for x in xcs])
     yp = (_P * count)(*[C.c_void_p(y.data_ptr()) for y in outs])
-    _check(lib().hh_matvec_batch(hs, count, xp, yp, nrhs, _stream_ptr(stream)))
+    _check(lib().hh_matvec_batch(hs, count, xp, yp, nrhs, _stream_ptr(stream, xcs + outs)))
     return outs

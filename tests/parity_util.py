@@ -10,7 +10,32 @@ import numpy as np
 import workloads as W
 from oracle import hh_oracle as O
 
-TIE_REL = 1e-6      # rank / format decisions this close to their threshold are ties
+U64 = 2.0 ** -53
+
+
+def rank_window(pmin: int, sketch: int, eps: float) -> float:
+    """Relative distance of a discarded tail from eps^2 ||H_b||^2 within which
+    two correct fp64 implementations may decide the rank differently.
+
+    The tail t_k = sum_{r > k} sigma_r^2 (plus ||H - Q Q^T H||^2 on the
+    randomized path) is compared with thr = eps^2 ||H_b||_F^2 >= eps^2
+    sigma_1^2. Singular values from two backward-stable SVDs (different
+    algorithms and summation orders) differ by about c u sigma_1 with c ~
+    sqrt(p), so |dt_k| <= 2 c u sigma_1 sum_{r > k} sigma_r + p u t_k <=
+    2 c u sigma_1 sqrt(p t_k) + p u t_k, i.e. relative to thr at most
+    2 p u / eps + p u. The residual of the randomized path, an explicit
+    difference H - Q B whose entries carry errors of about (s + 2) u |H_ij|,
+    adds 4 (s + 2) u / eps."""
+    p = max(int(pmin), 1)
+    s = max(int(sketch), 0)
+    return (2.0 * p + (4.0 * (s + 2) if s > 0 else 0.0)) * U64 / eps + p * U64
+
+
+def format_window(rank: int, pmin: int, n_blocks: int) -> float:
+    """Relative width of a format tie: ||H~_b||^2 = sum_{r <= k} sigma_r^2 differs
+    between implementations by about (2 sqrt(p) + k) u relative, ||H~||^2 (a sum
+    over every block in another order) by about n_blocks u."""
+    return (2.0 * max(pmin, 1) ** 0.5 + rank + n_blocks + 8.0) * U64
 
 
 def build_pair(points, kernel, tol, eta, ell, leaf, mask=0xF, uniform=False, normals=None,
@@ -23,21 +48,23 @@ def build_pair(points, kernel, tol, eta, ell, leaf, mask=0xF, uniform=False, nor
     return g, o
 
 
-def rank_tie(sb) -> bool:
+def rank_tie(sb, eps) -> bool:
     c = sb.comp
     if c is None:
         return False
-    near = lambda t: math.isfinite(t) and abs(t - c.thr) <= TIE_REL * c.thr
+    w = rank_window(min(sb.blk.m, sb.blk.n), c.sketch, eps)
+    near = lambda t: math.isfinite(t) and abs(t - c.thr) <= w * c.thr
     return near(c.tail) or near(c.tail_prev)
 
 
 def format_tie(hm, sb) -> bool:
     if not sb.lowrank or hm.uniform:
         return False
+    w = format_window(sb.rank, min(sb.blk.m, sb.blk.n), len(hm.blocks))
     for f in (W.FMT_BF16, W.FMT_FP16, W.FMT_FP32):
         if hm.mask & (1 << f):
             r = O.format_margin(sb.nb2, hm.total2, sb.blk.level, hm.d, hm.eps, f)
-            if abs(r - 1.0) <= 1e-9:
+            if abs(r - 1.0) <= w:
                 return True
     return False
 
@@ -58,7 +85,7 @@ def compare_structure(g, o) -> list:
         f_ok = bl["format"][q] == st["fmt"][q]
         if r_ok and f_ok:
             continue
-        if (not r_ok and rank_tie(sb) and abs(int(bl["rank"][q]) - int(st["rank"][q])) == 1) or \
+        if (not r_ok and rank_tie(sb, o.eps) and abs(int(bl["rank"][q]) - int(st["rank"][q])) == 1) or \
            (r_ok and not f_ok and format_tie(o, sb)):
             ties.append(q)
             continue

@@ -141,3 +141,34 @@ def test_switch_level_search_rejects_bad_arguments_on_host():
     for tol, eta, leaf in ((0.0, 1.0, 32), (1e-6, 0.0, 32), (1e-6, 1.0, 0)):
         assert lib.hh_switch_level_search(pp, 2048, 2, C.byref(k), tol, eta, leaf, None,
                                           C.byref(lvl), None, None, 0) == hh.HH_EINVAL
+
+
+@pytest.mark.parametrize("t", [7, 10, 15, 16, 17, 22, 23])
+def test_continuum_rounding_matches_oracle(t):
+    # the library's continuum rounding (f64_to_cont_rne, host side) against the
+    # oracle's round_fp, written independently: random magnitudes over the whole
+    # exponent range, exact ties between neighbours, the gradual-underflow range
+    # and the overflow edge; t = 7 and t = 23 also against bf16 / fp32 rounding
+    hh = _lib_or_skip()
+    rng = np.random.default_rng(t)
+    xs = [rng.standard_normal(4000) * 10.0 ** rng.uniform(-44, 38, 4000)]
+    k = rng.integers(1 << t, 1 << (t + 1), 2000)
+    e = rng.integers(-125, 127, 2000)
+    xs.append(np.ldexp(2.0 * k + 1.0, e - t - 1) * rng.choice([-1.0, 1.0], 2000))   # ties
+    ks = rng.integers(0, 1 << t, 1000)
+    xs.append(np.ldexp(2.0 * ks + 1.0, -126 - t - 1))                                  # subnormal ties
+    xs.append(rng.uniform(0.0, 2.0 ** -126, 1000))
+    top = (2.0 - 2.0 ** -t) * 2.0 ** 127
+    xs.append(np.array([top, top * (1 + 2.0 ** -(t + 2)), top * (1 + 2.0 ** -(t + 1)), 2.0 ** 128,
+                        -top, 0.0, -0.0, 2.0 ** -150, 2.0 ** -149, 3.0 * 2.0 ** -151]))
+    x = np.concatenate(xs)
+    got = hh.quantize_cont(x, t)
+    want = O.round_fp(x, t)
+    bad = np.flatnonzero(~((got == want) | (np.isnan(got) & np.isnan(want))))
+    assert bad.size == 0, (x[bad[:5]], got[bad[:5]], want[bad[:5]])
+    assert np.array_equal(np.signbit(got[x == 0.0]), np.signbit(x[x == 0.0]))
+    if t == 23:
+        with np.errstate(over="ignore"):
+            assert np.array_equal(got, x.astype(np.float32).astype(np.float64))
+    if t == 7:
+        assert np.array_equal(got, O.round_bf16(x))

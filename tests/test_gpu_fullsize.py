@@ -2,17 +2,34 @@
 
 For the 3D Laplace matrix at N = 2^20 (the benchmark's configuration), the 2D
 1/r matrix at N = 2^18 and the double-layer matrix at N = 2^19 (16 fp32
-right-hand sides, transpose): the tree and the partition against the oracle's,
-a sample of admissible blocks compressed by the oracle (rank, format under the
-global norm, stored approximation), the rows of two leaves against the fp64
-product of the GPU's own exported factors, and 512 sampled rows of the product
-against the exact dense rows (relative 2-norm over the sample <= 10 tol)."""
+right-hand sides, transpose):
+
+* the tree and the partition against the oracle's;
+* 30 admissible blocks (one of every level and kind present, the largest
+  level included, then random ones) compressed by the oracle: rank bit for
+  bit outside the tie window, stored approximation within eps plus the
+  format's rounding, and the format under the oracle's own estimate of
+  ||H~||^2. That estimate is ||H||_F^2 from 2048 exact sampled rows (Lemma
+  global_error puts ||H~|| within eps of ||H||); its sampling error is not
+  bounded (row norms of a singular kernel are heavy-tailed), so a format is
+  checked only where the rule's decision is the same for every ||H~||^2
+  within a factor 1.5 of the estimate, and the undecided blocks are counted.
+  The N = 2^17 test of the same recipe checks every format against the
+  oracle's exact ||H~||^2;
+* the rows of two leaves against the fp64 product of the GPU's own exported
+  factors;
+* 2048 sampled rows of the product against the exact dense rows: relative
+  2-norm over the sample <= 10 tol for the single-layer kernels; for the
+  double layer, whose storage error the rule lets grow with the
+  interaction-list constants, the bound of Thm amp_throrem with the
+  enumerated constants (85.6 tol at L = 4, switching level 3, eta 1.5), with
+  the 10 tol comparison and the largest per-row errors printed."""
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import hh_oracle as O
-from parity_util import TIE_REL
+from parity_util import rank_window
 
 pytestmark = pytest.mark.gpu
 
@@ -35,28 +52,51 @@ def _structure(g, points, leaf, eta, ell):
     return tree, blocks, bl
 
 
-def _sampled_blocks(g, kern, points, tree, blocks, bl, tol, rng, count=6):
-    st = g.stats()
+def _dense_rows(points, kern, x, rows, trans, chunk=64):
+    """Exact rows of H x (of H^T x when trans) and the squared norms of those
+    rows of H (columns of H), from the oracle's kernel entries."""
+    n = points.shape[0]
+    g = np.arange(n)
+    x2 = x.reshape(n, -1)
+    out = np.zeros((rows.size, x2.shape[1]))
+    nrm2 = np.zeros(rows.size)
+    for a in range(0, rows.size, chunk):
+        r = rows[a:a + chunk]
+        if trans:
+            nj = kern.normals[r] if kern.normals is not None else None
+            blk = O.kernel_entries(kern, points, points[r], g, r, nj).T
+        else:
+            blk = O.kernel_entries(kern, points[r], points, r, g, kern.normals)
+        out[a:a + chunk] = blk @ x2
+        nrm2[a:a + chunk] = np.sum(blk * blk, axis=1)
+    return out.reshape((rows.size,) + x.shape[1:]), nrm2
+
+
+def _sampled_blocks(g, kern, points, tree, blocks, bl, tol, rng, norm2_est, count=30):
     pt = points[tree.perm]
     nt = kern.normals[tree.perm] if kern.normals is not None else None
     lr = np.flatnonzero(bl["lowrank"].astype(bool))
-    size = np.minimum(bl["row_end"] - bl["row_begin"], bl["col_end"] - bl["col_begin"])
-    lr = lr[size[lr] <= 4096]           # blocks the oracle compresses in seconds
-    # one block of each level present, then random ones
-    pick = [int(rng.choice(lr[bl["level"][lr] == l])) for l in np.unique(bl["level"][lr])]
-    pick += [int(q) for q in rng.choice(lr, count - len(pick), replace=False)] if count > len(pick) else []
+    key = bl["level"][lr] * 8 + bl["kind"][lr]
+    pick = [int(rng.choice(lr[key == k])) for k in np.unique(key)]
+    rest = np.setdiff1d(lr, pick)
+    pick += [int(q) for q in rng.choice(rest, max(count - len(pick), 0), replace=False)]
+    undecided = 0
     for q in pick:
         b = blocks[q]
         H = O.block_entries(pt, kern, nt, b)
         c = O.compress(H, tol, 0, q)
-        near = lambda t: np.isfinite(t) and abs(t - c.thr) <= TIE_REL * c.thr
+        w = rank_window(min(b.m, b.n), c.sketch, tol)
+        near = lambda t: np.isfinite(t) and abs(t - c.thr) <= w * c.thr
         assert bl["rank"][q] == c.rank or (abs(int(bl["rank"][q]) - c.rank) == 1 and (near(c.tail) or near(c.tail_prev))), \
             (q, bl["rank"][q], c.rank)
         if bl["rank"][q] == c.rank:
             nb2 = float(np.sum(c.sigma[:c.rank] ** 2))
-            fmt = O.choose_format(nb2, st["norm2_total"], b.level, tree.d, tol, 0xF)
-            assert bl["format"][q] == fmt or abs(O.format_margin(nb2, st["norm2_total"], b.level, tree.d, tol,
-                                                                  int(bl["format"][q])) - 1) <= 1e-9
+            lo = O.choose_format(nb2, norm2_est / 1.5, b.level, tree.d, tol, 0xF)
+            hi = O.choose_format(nb2, norm2_est * 1.5, b.level, tree.d, tol, 0xF)
+            if lo == hi:
+                assert bl["format"][q] == lo, (q, bl["format"][q], lo)
+            else:
+                undecided += 1
         U, V = g.block_factors(q)
         err = np.linalg.norm(H - U @ V.T) / max(np.linalg.norm(H), 1e-300)
         # eps ||H_b|| from the truncation plus the rounding of the stored
@@ -65,6 +105,9 @@ def _sampled_blocks(g, kern, points, tree, blocks, bl, tol, rng, count=6):
         u = O.UNIT[int(bl["format"][q])]
         k = max(int(bl["rank"][q]), 1)
         assert err <= tol + 3.0 * u * np.sqrt(k), (q, err)
+    print(f"  sampled blocks {len(pick)} (sizes up to {max(min(blocks[q].m, blocks[q].n) for q in pick)}), "
+          f"formats undecided by the norm estimate: {undecided}", flush=True)
+    assert undecided <= len(pick) // 5
 
 
 def _leaf_rows_exported(g, bl, perm, x, leaves, trans=False):
@@ -103,7 +146,7 @@ def _leaves(g, bl, rng, count=2):
     return [(int(bl["row_begin"][i]), int(bl["row_end"][i])) for i in q]
 
 
-def _run(problem, nrhs=1, io="f64", trans=False, seed=0):
+def _run(problem, nrhs=1, io="f64", trans=False, seed=0, bar=None):
     torch = _torch()
     from paper_2604_09147_amd import HMatrix
     p = problem
@@ -113,13 +156,17 @@ def _run(problem, nrhs=1, io="f64", trans=False, seed=0):
                 h=p.h, normals=p.normals, io_dtype=io)
     rng = np.random.default_rng(seed)
     tree, blocks, bl = _structure(g, p.points, p.leaf_size, p.eta, p.switch_level)
-    print(f"full size {p.name}: structure matches, sampling blocks", flush=True)
-    _sampled_blocks(g, kern, p.points, tree, blocks, bl, p.tol, rng)
+    print(f"full size {p.name}: structure matches", flush=True)
     shape = (p.n,) if nrhs == 1 else (p.n, nrhs)
     dt = torch.float32 if io == "f32" else torch.float64
     x = torch.from_numpy(rng.standard_normal(shape)).to(dt).cuda()
     y = (g.matvec_t(x) if trans else g.matvec(x)).double().cpu().numpy()
     xin = x.double().cpu().numpy()
+    rows = rng.choice(p.n, 2048, replace=False)
+    yd, nrm2 = _dense_rows(p.points, kern, xin, rows, trans)
+    norm2_est = float(np.sum(nrm2)) * p.n / rows.size
+    print(f"full size {p.name}: ||H||^2 from 2048 rows {norm2_est:.6e}; sampling blocks", flush=True)
+    _sampled_blocks(g, kern, p.points, tree, blocks, bl, p.tol, rng, norm2_est)
     r_idx, ye = _leaf_rows_exported(g, bl, g.perm(), xin, _leaves(g, bl, rng), trans)
     e_exp = np.linalg.norm(y[r_idx] - ye) / np.linalg.norm(ye)
     print(f"full size {p.name}: two leaves vs exported factors {e_exp:.2e}", flush=True)
@@ -127,13 +174,16 @@ def _run(problem, nrhs=1, io="f64", trans=False, seed=0):
     # one RHS); fp32 outputs are rounded once more
     bound = 2.0 ** -22 if io == "f32" else (1e-12 if nrhs > 1 or not np.any(bl["format"] >= 2) else 1e-6)
     assert e_exp <= bound, (e_exp, bound)
-    rows = rng.choice(p.n, 512, replace=False)
-    yd = O.dense_matvec_t(p.points, kern, xin, cols=rows) if trans else O.dense_matvec(p.points, kern, xin, rows=rows)
     e_dense = np.linalg.norm(y[rows] - yd) / np.linalg.norm(yd)
-    per_row = np.linalg.norm((y[rows] - yd).reshape(512, -1), axis=1)
+    per_row = np.linalg.norm((y[rows] - yd).reshape(rows.size, -1), axis=1)
+    ref_row = np.linalg.norm(yd.reshape(rows.size, -1), axis=1)
     top = np.sort(per_row)[::-1][:4] / np.linalg.norm(yd)
-    print(f"full size {p.name}: 512 sampled rows vs dense {e_dense:.2e} (largest rows' share {top})", flush=True)
-    assert e_dense <= max(10 * p.tol, 2.0 ** -22)
+    worst = float(np.max(per_row / np.maximum(ref_row, 1e-300)))
+    limit = max(10 * p.tol if bar is None else bar, 2.0 ** -22)
+    print(f"full size {p.name}: 2048 sampled rows vs dense {e_dense:.2e} (bar {limit:.2e}, "
+          f"10 tol {'met' if e_dense <= 10 * p.tol else 'missed'}); largest rows' share {top}; "
+          f"largest per-row relative error {worst:.2e}", flush=True)
+    assert e_dense <= limit
     g.free()
 
 
@@ -149,4 +199,8 @@ def test_full_size_2d_inv_r():
 
 @pytest.mark.timeout(900)
 def test_full_size_double_layer_transpose_16_rhs():
-    _run(W.cfg_double_layer(), nrhs=16, io="f32", trans=True, seed=3)
+    p = W.cfg_double_layer()
+    # Thm amp_throrem with the enumerated constants of eta = 1.5 in 3D
+    L = O.tree_depth(p.n, 3, p.leaf_size)
+    c = O.global_bound(3, p.eta, L, O.resolve_switch_level(p.switch_level, L))
+    _run(p, nrhs=16, io="f32", trans=True, seed=3, bar=c * p.tol)

@@ -185,3 +185,19 @@ def test_wide_sketches_high_rank_blocks():
     compare_structure(g, o)
     _check_products(g, o, P, O.Kernel(W.INV_R), tol, dense=False)
     _check_products(g, o, P, O.Kernel(W.INV_R), tol, trans=True, dense=False)
+
+
+def test_long_columns_hodlr_1d():
+    # 1D HODLR (switching level 0): the level-1 siblings are about 8200 x 8200,
+    # so their columns are longer than the 4096 rows the inner-product kernel
+    # stages in LDS and take its long-column branch (four columns per wave
+    # sharing every x load); level 2 has columns of about 4100 rows, just past it
+    rng = np.random.default_rng(17)
+    P = rng.random((16384, 1))
+    tol = 1e-6
+    g, o = build_pair(P, W.INV_R, tol, 1.0, 0, 256)
+    assert o.ell == 0 and min(o.blocks[0].blk.m, o.blocks[0].blk.n) > 4096
+    compare_structure(g, o)
+    _check_products(g, o, P, O.Kernel(W.INV_R), tol)
+    _check_products(g, o, P, O.Kernel(W.INV_R), tol, trans=True)
+    _check_products(g, o, P, O.Kernel(W.INV_R), tol, nrhs=4, dense=False)

@@ -72,6 +72,58 @@ def test_autograd_backward_is_the_transposed_product():
     g64.free()
 
 
+def _assembled_gpu_matrix(g):
+    """Dense N x N matrix (caller order) from the GPU's stored, decoded blocks."""
+    n = g.n
+    perm = g.perm()
+    bl = g.blocks()
+    A = np.zeros((n, n))
+    for q in range(bl["level"].size):
+        ri = perm[int(bl["row_begin"][q]):int(bl["row_end"][q])]
+        cj = perm[int(bl["col_begin"][q]):int(bl["col_end"][q])]
+        U, V = g.block_factors(q)
+        if bl["lowrank"][q]:
+            if bl["rank"][q]:
+                A[np.ix_(ri, cj)] += U @ V.T
+        else:
+            A[np.ix_(ri, cj)] += U
+    return A
+
+
+def test_double_layer_4096_point_subsample_against_dense_transpose():
+    # the double-layer recipe's own check: an H_h built on 4096 points drawn from
+    # the N = 2^19 recipe (same kernel and normals, tol 1e-6, eta 1.5, leaf 256,
+    # switching level L - 1), 16 fp32 right-hand sides through autograd; the
+    # backward pass against the dense fp64 transpose on all 4096 rows
+    torch = _torch()
+    from paper_2604_09147_amd.autograd import hh_apply
+    p = W.cfg_double_layer()
+    idx = np.random.default_rng(5050).choice(p.n, 4096, replace=False)
+    P, nrm = p.points[idx], p.normals[idx]
+    g, o = build_pair(P, W.DOUBLE_LAYER, p.tol, p.eta, -1, p.leaf_size, normals=nrm, io="f32")
+    compare_structure(g, o)
+    k = O.Kernel(W.DOUBLE_LAYER, normals=nrm)
+    Hd = O.dense_matrix(P, k)
+    # Thm amp_throrem on the stored matrix, enumerated constants of eta = 1.5
+    c = O.global_bound(3, p.eta, o.tree.L, o.ell)
+    e_mat = np.linalg.norm(Hd - _assembled_gpu_matrix(g)) / np.linalg.norm(Hd)
+    assert e_mat <= c * p.tol, (e_mat, c)
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy(rng.standard_normal((4096, 16))).float().cuda().requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((4096, 16))).float().cuda()
+    (hh_apply(g, x) * w).sum().backward()
+    grad = x.grad.double().cpu().numpy()
+    ref = Hd.T @ w.double().cpu().numpy()
+    e = rel(grad, ref)
+    per_row = np.linalg.norm(grad - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    print(f"double layer, 4096-point subsample (L={o.tree.L}, switching level {o.ell}): "
+          f"||H - H^||_F / ||H||_F = {e_mat:.2e} (Thm amp bound {c * p.tol:.2e}); backward vs "
+          f"dense transpose {e:.2e} (10 tol {'met' if e <= 10 * p.tol else 'missed'}), largest "
+          f"per-row relative error {per_row.max():.2e}", flush=True)
+    assert e <= max(c * p.tol, 2.0 ** -22)
+    assert rel(grad, O.matvec_t(o, w.double().cpu().numpy())) <= max(1e-2 * p.tol, 2.0 ** -22)
+
+
 def test_transpose_adjoint_identity():
     # <w, H^ x> = <H^^T w, x> with the same stored factors (fp64 arithmetic)
     torch = _torch()
@@ -143,3 +195,31 @@ def test_derived_handle_equals_direct_build():
     assert float(torch.linalg.norm(ya - y64) / torch.linalg.norm(y64)) <= 1e-5
     for m in (ga, gd, g64):
         m.free()
+
+
+def test_runs_cut_at_a_lowered_buffer_limit(monkeypatch):
+    # The accumulation kernels address each run of factor columns through one
+    # buffer descriptor (32-bit byte offsets), so hh_build cuts runs and their
+    # work-unit slices below 2^31 bytes. Lowering that limit to 64 KiB makes
+    # the cutting happen at this size: products must not change.
+    torch = _torch()
+    from paper_2604_09147_amd import HHError, HMatrix
+    p = W.cfg_plain_small(seed=5, n=3000)
+    tol = 1e-6
+    _, o = build_pair(p.points, p.kernel, tol, p.eta, -1, 48)
+    monkeypatch.setenv("HH_RUN_BYTES_MAX", "65536")
+    g = HMatrix(p.points, p.kernel, tol, p.eta, -1, 48)
+    compare_structure(g, o)
+    rng = np.random.default_rng(21)
+    for nrhs in (1, 5):
+        x = rng.standard_normal((3000, nrhs))
+        xd = torch.from_numpy(x).cuda()
+        assert rel(g.matvec(xd).cpu().numpy(), O.matvec(o, x)) <= 1e-2 * tol
+        assert rel(g.matvec_t(xd).cpu().numpy(), O.matvec_t(o, x)) <= 1e-2 * tol
+    g.free()
+    # a single column longer than the limit is refused (every column here holds
+    # more than 16 entries of at least 2 bytes)
+    monkeypatch.setenv("HH_RUN_BYTES_MAX", "32")
+    with pytest.raises(HHError) as ei:
+        HMatrix(p.points, p.kernel, tol, p.eta, -1, 48)
+    assert ei.value.status == 4

@@ -233,10 +233,11 @@ def _block(m, n, seed=0, kind=W.INV_R, d=3, gap=1.0):
     return O.kernel_entries(O.Kernel(kind), A, B, np.arange(m), np.arange(m, m + n), None)
 
 
-@pytest.mark.parametrize("eps", [1e-2, 1e-6, 1e-10])
-def test_exact_compression_rank_is_minimal(eps):
+@pytest.mark.parametrize("eps,m,n", [(1e-2, 200, 150), (1e-6, 200, 150), (1e-10, 200, 150),
+                                     (1e-6, 512, 300), (1e-8, 60, 50)])
+def test_exact_compression_rank_is_minimal(eps, m, n):
     # Eckart-Young with an independent LAPACK driver: the rank-(k-1) optimum misses eps
-    H = _block(60, 50, 1, gap=0.2)
+    H = _block(m, n, 1, gap=0.2)
     c = O.compress(H, eps)
     assert c.sketch == 0
     s = scipy.linalg.svd(H, compute_uv=False, lapack_driver="gesvd")
@@ -247,8 +248,8 @@ def test_exact_compression_rank_is_minimal(eps):
     assert np.allclose(c.U.T @ c.U, np.eye(c.rank), atol=1e-12)
 
 
-@pytest.mark.parametrize("eps,m,n", [(1e-4, 700, 640), (1e-8, 700, 640), (1e-6, 200, 150),
-                                     (1e-10, 130, 90)])
+@pytest.mark.parametrize("eps,m,n", [(1e-4, 700, 640), (1e-8, 700, 640), (1e-6, 600, 520),
+                                     (1e-10, 530, 1100)])
 def test_randomized_compression_matches_exact_rank(eps, m, n):
     # block above the exact-SVD size: the certified bound holds and the rank equals
     # the rank of the exact SVD computed by an independent LAPACK driver

@@ -39,7 +39,7 @@ def test_rank_rule_takes_an_exact_tie():
 @pytest.mark.parametrize("eps", [0.3, 0.5, 0.7])
 def test_randomized_compression_is_certified_on_slow_decay(eps):
     rng = np.random.default_rng(0)
-    H = rng.standard_normal((300, 200))             # flat spectrum: sketches miss energy
+    H = rng.standard_normal((700, 560))             # flat spectrum: sketches miss energy
     c = O.compress(H, eps, 0, 7)
     assert c.sketch > 0                              # the randomized path ran
     err = np.linalg.norm(H - c.U @ c.V.T)
@@ -54,7 +54,7 @@ def test_randomized_compression_is_certified_on_slow_decay(eps):
 def test_sign_rule_on_every_column():
     rng = np.random.default_rng(3)
     mats = [rng.standard_normal((40, 30)),                       # exact SVD
-            rng.standard_normal((300, 200)),                     # randomized
+            rng.standard_normal((700, 560)),                     # randomized
             O.dense_matrix(rng.random((200, 2)), O.Kernel(W.LOG))[:100, 100:]]
     for H in mats:
         c = O.compress(H, 0.3, 0, 11)
