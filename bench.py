@@ -255,6 +255,8 @@ def main() -> int:
                     help="right-hand-side counts timed on the adaptive handle after the "
                          "single-vector product ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default task sizes instead of the tuned ones")
     ap.add_argument("--no-uniform", action="store_true", help="build the adaptive handle only")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-check", action="store_true",
@@ -308,6 +310,15 @@ def main() -> int:
 
     x = torch.from_numpy(W.rhs(p.n, 1, np.random.default_rng(1))[:, 0].copy()).cuda()
 
+    tuned = {}
+
+    def tune(H, name):
+        if args.no_autotune:
+            return
+        r = H.autotune()
+        tuned[name] = r["best"]
+        print(f"bench: {name} task sizes {r['best']}", file=sys.stderr, flush=True)
+
     def run(H, xin):
         y = torch.empty_like(xin)
         wall, med = graph_timing(H, xin, y, args.steps, args.warmup)
@@ -315,6 +326,7 @@ def main() -> int:
         torch.cuda.synchronize()
         return y.clone(), wall, med, ph
 
+    tune(Ha, "adaptive")
     ya, el_a, med_a, ph_a = run(Ha, x)
     sa = Ha.stats()
     print(f"bench: adaptive {1e3 * el_a / args.steps:.3f} ms per product", file=sys.stderr, flush=True)
@@ -326,6 +338,7 @@ def main() -> int:
                         "hbm_gbs": sa["matvec_bytes"] / (el_a / args.steps) / 1e9,
                         "blocks_by_format": sa["blocks_by_format"]}}
     if H64 is not None:
+        tune(H64, "uniform_fp64")
         y6, el_6, med_6, ph_6 = run(H64, x)
         s6 = H64.stats()
         res["uniform_fp64"] = {"matvec_per_s": args.steps / el_6,
@@ -339,6 +352,7 @@ def main() -> int:
         res["adaptive_vs_uniform_rel_diff"] = float(torch.linalg.norm(ya - y6) / torch.linalg.norm(y6))
         # continuum storage (per block t fraction bits) of the same factors
         Hc = H64.derive(continuum=True)
+        tune(Hc, "continuum")
         yc, el_c, med_c, ph_c = run(Hc, x)
         sc = Hc.stats()
         bc = Hc.blocks()
@@ -437,7 +451,7 @@ def main() -> int:
                                   f"{p.tol}, adaptive fp64/fp32/fp16/bf16, nrhs 1",
                       "n": p.n, "nrhs": 1, "build_seconds": round(t_build, 2),
                       "timing": "graph replays", "parallelism": "1 GPU"},
-           "hbm_gbs": round(res["adaptive"]["hbm_gbs"], 1), "results": res,
+           "hbm_gbs": round(res["adaptive"]["hbm_gbs"], 1), "results": res, "autotune": tuned,
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     return 0

@@ -95,6 +95,10 @@ typedef struct {
                                 mask's formats: each block takes the fewest
                                 fraction bits t in [7, 23] whose unit roundoff
                                 2^-(t+1) passes the rule, else fp64             */
+    int64_t unit_bytes;      /* factor bytes per work unit of the single-vector
+                                accumulation; 0 = 1 MiB (hh_autotune picks one)  */
+    int64_t dot_task_elems;  /* stored entries per single-vector inner-product
+                                task; 0 = 65536 (hh_autotune picks one)         */
 } hh_options;
 
 typedef struct {
@@ -224,7 +228,8 @@ hh_status hh_matvec_timed(const hh_handle* h, const void* x, void* y, int64_t nr
 
 /* hh_matvec_batch: y_t = H_t^ x_t (Alg. 4) for `count` independent handles in
  * one pass of the kernels (one launch per phase over all handles). Every
- * handle must share io_dtype and the device; x[t], y[t] are DEVICE pointers
+ * handle must share io_dtype and the device, and either all or none of them
+ * may hold continuum storage (HH_ENOTSUP otherwise); x[t], y[t] are DEVICE pointers
  * sized for handle t (N_t x nrhs, row-major). The task tables of the last
  * batch (same handles in the same order, same nrhs) stay on the device, so a
  * repeated call only uploads the x / y descriptors on `stream` and returns
@@ -257,6 +262,51 @@ hh_status hh_matvec_batch(const hh_handle* const* hs, int count, const void* con
  * and other errors as for hh_matvec. */
 hh_status hh_matvec_noalloc(const hh_handle* h, const void* x, void* y, int64_t nrhs, int trans,
                             void* stream);
+
+/* hh_solve: restarted GMRES (Saad & Schultz) for (H^ + shift I) x = b, or
+ * (H^^T + shift I) x = b when trans != 0, with the handle's product as the
+ * operator: the iterative use of the fast product that closes Sec. 5.3.
+ * Krylov basis orthonormalised by classical Gram-Schmidt applied twice, least
+ * squares kept triangular by Givens rotations.
+ *   b, x       DEVICE, N fp64 in caller order (handle with HH_IO_F64, else
+ *              HH_ENOTSUP); x holds the initial guess on entry (zero it for
+ *              none) and the solution on return. b and x must not alias.
+ *   shift      real diagonal shift (0 for H^ itself).
+ *   rtol       stop when ||b - A x|| <= rtol ||b|| (the recurrence's residual
+ *              inside a cycle, the true residual between cycles).
+ *   restart    Krylov dimension per cycle, 1..1000; max_iter >= 0 products.
+ *   iters      HOST, receives the number of Krylov steps (may be NULL).
+ *   relres     HOST, receives ||b - A x|| / ||b|| recomputed after the last
+ *              cycle (may be NULL).
+ * Runs on `stream` and returns after synchronising it; allocates its basis
+ * (8 N (restart + 1) bytes) for the call. */
+hh_status hh_solve(const hh_handle* h, const void* b, void* x, double shift, double rtol,
+                   int restart, int max_iter, int trans, int32_t* iters, double* relres,
+                   void* stream);
+
+/* One setting of the task-table sizes and its measured product time. */
+typedef struct {
+    int64_t unit_bytes;      /* factor bytes per single-vector accumulation unit */
+    int64_t dot_task_elems;  /* stored entries per single-vector inner-product task */
+    double ms;               /* median time of one y = H^ x product, milliseconds */
+} hh_tuning;
+
+/* hh_autotune: picks the task-table sizes of the single-vector product for
+ * this handle by measurement: work units of 256 KiB .. 4 MiB of factor data
+ * with the default inner-product tasks, then inner-product tasks of 16K ..
+ * 256K stored entries with the best unit size; each setting gets new task
+ * tables (host work, no change to the stored matrix) and five timed products
+ * after a warm-up (median of HIP events on `stream`, synchronised). The
+ * handle keeps the fastest setting (the tables of both directions are rebuilt
+ * with it); pass best->unit_bytes / dot_task_elems as hh_options of later
+ * builds of similar matrices to skip the search. Products of any nrhs stay
+ * correct; several-RHS tiles are not affected. Allocates temporary x, y.
+ *   best       HOST, receives the chosen setting (not NULL).
+ *   tried      HOST array of cap entries (may be NULL): every setting timed,
+ *              in order; ntried (may be NULL) receives their number.
+ * Must not overlap other calls on the handle; drops the cached batch tables. */
+hh_status hh_autotune(hh_handle* h, void* stream, hh_tuning* best, hh_tuning* tried,
+                      int32_t cap, int32_t* ntried);
 
 /* hh_reserve: size the product workspace for up to max_nrhs right-hand sides
  * now (products with larger nrhs allocate on first use, which is not allowed

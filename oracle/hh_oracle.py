@@ -998,3 +998,75 @@ def optimal_switch_level(points: np.ndarray, kern: Kernel, eps: float, eta: floa
     ell, gains = switch_level_search(L, s1, s2_fn)
     return {"ell": ell, "L": L, "s1": s1, "s2": s2, "gains": gains,
             "storage_hs": storage(hs)["total"]}
+
+
+# --------------------------------------------------------------------------
+# Iterative solution with the H_h matrix (the closing remark of Sec. 5.3: the
+# fast mixed-precision product serves iterative solvers). Restarted GMRES
+# (Saad & Schultz, 1986) for (H^ + shift I) x = b, the Krylov basis made
+# orthonormal by classical Gram-Schmidt applied twice, the small least-squares
+# problem kept triangular with Givens rotations.
+# --------------------------------------------------------------------------
+def gmres(apply, b: np.ndarray, x0: np.ndarray | None = None, rtol: float = 1e-10,
+          restart: int = 30, max_iter: int = 300) -> tuple:
+    """Returns (x, iterations, relative residual history) for the operator
+    `apply` (a function v -> A v). The residual history holds the recurrence's
+    residual norms divided by ||b||, one per iteration, after the initial one;
+    the method stops when that ratio is <= rtol or after max_iter iterations."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    if nb == 0.0:
+        return np.zeros(n), 0, [0.0]
+    hist = []
+    it = 0
+    while True:
+        r = b - apply(x)
+        beta = float(np.linalg.norm(r))
+        hist.append(beta / nb)
+        if beta / nb <= rtol or it >= max_iter:
+            return x, it, hist
+        m = min(restart, max_iter - it)
+        V = np.zeros((n, m + 1))
+        Hs = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[:, 0] = r / beta
+        k = 0
+        for j in range(m):
+            w = apply(V[:, j])
+            h = V[:, :j + 1].T @ w
+            w = w - V[:, :j + 1] @ h
+            h2 = V[:, :j + 1].T @ w
+            w = w - V[:, :j + 1] @ h2
+            h = h + h2
+            hn = float(np.linalg.norm(w))
+            Hs[:j + 1, j] = h
+            Hs[j + 1, j] = hn
+            if hn > 0.0:
+                V[:, j + 1] = w / hn
+            for i in range(j):                      # earlier rotations
+                a, c = Hs[i, j], Hs[i + 1, j]
+                Hs[i, j] = cs[i] * a + sn[i] * c
+                Hs[i + 1, j] = -sn[i] * a + cs[i] * c
+            a, c = Hs[j, j], Hs[j + 1, j]
+            d = math.hypot(a, c)
+            cs[j], sn[j] = (1.0, 0.0) if d == 0.0 else (a / d, c / d)
+            Hs[j, j] = d
+            Hs[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            res = abs(g[j + 1]) / nb
+            if res <= rtol or hn == 0.0:
+                break
+            if j + 1 < m:
+                hist.append(res)
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):              # back substitution
+            y[i] = (g[i] - Hs[i, i + 1:k] @ y[i + 1:]) / Hs[i, i]
+        x = x + V[:, :k] @ y

@@ -18,7 +18,7 @@ LIB = os.path.join(LIBDIR, "libhhmat.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "capi.cpp", "build.hip", "kernels_build.hip", "kernels_mv.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "solve.cpp", "build.hip", "kernels_build.hip", "kernels_mv.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{os.path.join(HERE, '..', 'include')}",
           f"-I{ROCM}/include", "-Wall", "-Wno-unused-function"]
@@ -29,7 +29,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 def _compile(src: str, obj: str) -> None:
     path = os.path.join(SRC, src)
     cmd = [os.path.join(ROCM, "bin", "hipcc")] + COMMON
-    if src.endswith(".hip") or src == "capi.cpp":
+    if src.endswith(".hip") or src in ("capi.cpp", "solve.cpp"):
         cmd += ["-x", "hip"] + DEVICE
     else:
         cmd += ["-x", "c++"]

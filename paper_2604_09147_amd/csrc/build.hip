@@ -49,7 +49,7 @@ constexpr int EXACT_SVD_MAX = 512;
 constexpr int SKETCH_START = 64;
 constexpr int OVERSAMPLE = 16;
 constexpr int64_t SUM_CHUNK = 65536;
-constexpr int64_t UNIT_BYTES = 1 << 20;   // factor bytes per single-vector work unit
+constexpr int64_t UNIT_BYTES = 1 << 20;   // default factor bytes per single-vector work unit
 // The accumulation kernels address a run through one buffer descriptor with
 // 32-bit byte offsets, so a run (and every slice of one) spans fewer than 2^31
 // bytes: longer runs are cut by columns. HH_RUN_BYTES_MAX may lower the limit
@@ -62,7 +62,7 @@ static int64_t run_bytes_max() {
     }
     return lim;
 }
-constexpr int64_t DOT_TASK_ELEMS = 65536;
+constexpr int64_t DOT_TASK_ELEMS = 65536;   // default elements per phase-V task
 constexpr int64_t DOT_X_LDS = 4096;        // rows of x staged in LDS by dot1_kernel
 
 void* DevMem::alloc(size_t bytes, bool zero) {
@@ -805,6 +805,7 @@ struct Builder {
         }
         bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0 && need[4] == 0;
         h->all_fp64 = all64;
+        h->has_cont = need[HH_FMT_CONT] > 0;
         if (all64 && in_place_ok) {
             // The fp64 store can serve as the arena as it is; it is re-laid in
             // cluster order (longer runs in the product) only if a second copy
@@ -973,9 +974,32 @@ static int64_t slice_bytes(const Run& rn, int64_t P) {
     return rn.fmt == HH_FMT_CONT ? (P * rn.w + 7) / 8 : P * (int64_t)fmt_size(rn.fmt);
 }
 
+// Partial-row buffer of the work units, grown to the current tables' need.
+static void ensure_part(hh_handle* h) {
+    if (h->part && h->part_rows <= h->part_cap) return;
+    const int64_t rows = std::max<int64_t>(h->part_rows, 1);
+    double* p = static_cast<double*>(h->mem.alloc((size_t)rows * 8 + 256, true));
+    if (h->part) h->mem.release(h->part);
+    h->part = p;
+    h->part_cap = rows;
+}
+
+// Frees the device copies of a direction's task tables (before a rebuild).
+static void drop_tasks(hh_handle* h, TaskSet& S) {
+    for (void* p : {(void*)S.d_dot, (void*)S.d_dotm, (void*)S.d_leaf, (void*)S.d_runs,
+                    (void*)S.d_cl_run, (void*)S.d_unit, (void*)S.d_uruns, (void*)S.d_fin})
+        if (p) h->mem.release(p);
+    S = TaskSet{};
+}
+
 static void build_tasks(hh_handle* h) {
     const Plan& P = h->plan;
     const int L = P.L, d = P.d;
+    const int64_t UNIT_BYTES = h->unit_bytes > 0 ? h->unit_bytes : hh::UNIT_BYTES;
+    const int64_t DOT_TASK_ELEMS = h->dot_task_elems > 0 ? h->dot_task_elems : hh::DOT_TASK_ELEMS;
+    drop_tasks(h, h->fwd);
+    drop_tasks(h, h->bwd);
+    h->part_rows = 0;
     const std::vector<int64_t> ord_f = direction_order(h, false), ord_t = direction_order(h, true);
     int64_t col = 0, col_t = 0;
     for (int64_t i : ord_f) {
@@ -1046,8 +1070,15 @@ static void build_tasks(hh_handle* h) {
     const int64_t ncl = first[L + 1];
     const int64_t nleaf = (int64_t)1 << (d * L);
     // transposed copies of the dense blocks: the product with H^T applies them
-    // as ordinary runs of the column cluster
-    {
+    // as ordinary runs of the column cluster (made once; a rebuild of the
+    // tables keeps them)
+    bool have_t = false;
+    for (const auto& r : h->blocks)
+        if (!r.lowrank) {
+            have_t = r.dt_ptr != nullptr;
+            break;
+        }
+    if (!have_t) {
         int64_t total = 0;
         for (const auto& r : h->blocks)
             if (!r.lowrank) total += r.PJ * (r.b.ie - r.b.ib);
@@ -1339,6 +1370,15 @@ static void fill_stats(hh_handle* h, double seconds) {
     s.build_seconds = seconds;
 }
 
+// New task tables with the given sizes (0 = default); the tuner's step.
+void retask(hh_handle* h, int64_t unit_bytes, int64_t dot_task_elems) {
+    HIPCHK(hipDeviceSynchronize());
+    h->unit_bytes = unit_bytes;
+    h->dot_task_elems = dot_task_elems;
+    build_tasks(h);
+    ensure_part(h);
+}
+
 hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel* k, double tol,
                         double eta, int switch_level, int leaf_size, const hh_options* opt) {
     auto t0 = std::chrono::steady_clock::now();
@@ -1355,9 +1395,24 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
     if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
     if (o.continuum != 0 && o.continuum != 1) fail(HH_EINVAL, "continuum must be 0 or 1");
+    if (o.unit_bytes < 0 || o.dot_task_elems < 0) fail(HH_EINVAL, "task sizes must be >= 0");
 
+    // wall time of each stage, printed when HH_VERBOSE is set
+    auto tstage = t0;
+    auto stage = [&](const char* what) {
+        if (!Builder::verbose()) return;
+        (void)hipDeviceSynchronize();
+        const auto now = std::chrono::steady_clock::now();
+        fprintf(stderr, "hh: build stage %-12s %8.3f s\n", what,
+                std::chrono::duration<double>(now - tstage).count());
+        fflush(stderr);
+        tstage = now;
+    };
     std::unique_ptr<hh_handle> h(new hh_handle());
+    h->unit_bytes = o.unit_bytes;
+    h->dot_task_elems = o.dot_task_elems;
     h->plan = make_plan(points, n, d, eta, switch_level, leaf_size);
+    stage("plan");
     HIPCHK(hipGetDevice(&h->device));
     h->tol = tol;
     h->opt = o;
@@ -1388,8 +1443,10 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
         h->d_pmap = upload(h->mem, pmap);
     }
 
+    stage("upload");
     Builder B(h.get());
     B.init();
+    stage("init");
     std::vector<int64_t> cand, dense_list, near_adaptive;
     for (size_t i = 0; i < h->blocks.size(); ++i) {
         BlockRec& r = h->blocks[i];
@@ -1403,7 +1460,9 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
         }
     }
     B.compress(cand);
+    stage("compress");
     B.dense(dense_list);
+    stage("dense");
 
     // Alg. 5: ||H~||^2; leaf neighbours of an H_s matrix enter with ||H_IJ||^2
     double total2 = 0.0;
@@ -1436,11 +1495,13 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
         r.nb2 = e2;
     }
     B.pack();
+    stage("pack");
     build_tasks(h.get());
+    stage("tasks");
     h->ws_R = 1;
     h->xt = static_cast<double*>(h->mem.alloc((size_t)h->np * 8 + 256, true));
     h->tb = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->ncols, 1) * 8 + 256, true));
-    h->part = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->part_rows, 1) * 8 + 256, true));
+    ensure_part(h.get());
     if (h->all_fp64) {
         // the fp64 store chunks are the arena: hand their ownership to the handle
         for (void* p : B.store.ptrs) h->mem.ptrs.push_back(p);
@@ -1466,6 +1527,7 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
     if (o.continuum != 0 && o.continuum != 1) fail(HH_EINVAL, "continuum must be 0 or 1");
+    if (o.unit_bytes < 0 || o.dot_task_elems < 0) fail(HH_EINVAL, "task sizes must be >= 0");
     if (!src->all_fp64) fail(HH_ENOTSUP, "hh_derive needs a source whose factors are all fp64");
     for (const auto& r : src->blocks)
         if (r.b.kind == HH_BLK_DENSE_NEAR)
@@ -1481,6 +1543,9 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     h->leaf_psz = src->leaf_psz;
     h->tpad = src->tpad;
     h->blocks = src->blocks;
+    h->unit_bytes = o.unit_bytes;
+    h->dot_task_elems = o.dot_task_elems;
+    for (auto& r : h->blocks) r.dt_ptr = nullptr;      // own transposed copies
     h->d_tpad = upload(h->mem, h->tpad);
     {
         std::vector<int64_t> pmap(h->np, -1);
@@ -1518,7 +1583,7 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     h->ws_R = 1;
     h->xt = static_cast<double*>(h->mem.alloc((size_t)h->np * 8 + 256, true));
     h->tb = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->ncols, 1) * 8 + 256, true));
-    h->part = static_cast<double*>(h->mem.alloc((size_t)std::max<int64_t>(h->part_rows, 1) * 8 + 256, true));
+    ensure_part(h.get());
     HIPCHK(hipDeviceSynchronize());
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(h.get(), secs);

@@ -87,13 +87,14 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     }
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
-    if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
-    else launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, stream);
+    if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->has_cont, stream);
+    else launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->has_cont, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[2], (hipStream_t)stream));
     if (R == 1)
-        launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(), stream);
+        launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(),
+                     h->has_cont, stream);
     else
-        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, stream);
+        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, h->has_cont, stream);
     HIPCHK(hipGetLastError());
     if (phase_ms) {
         HIPCHK(hipEventRecord(ev[3], (hipStream_t)stream));
@@ -106,6 +107,14 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
         for (auto& e : ev) (void)hipEventDestroy(e);
     }
 }
+
+// The product for the solver (same checks and kernels as hh_matvec).
+void apply_product(const hh_handle* h, const void* x, void* y, int64_t nrhs, void* stream, bool trans) {
+    product(h, x, y, nrhs, stream, trans);
+}
+
+void gmres(const hh_handle* h, const double* b, double* x, double shift, double rtol, int restart,
+           int max_iter, int trans, int32_t* iters, double* relres, void* stream);
 
 // Workspace of hh_matvec_noalloc: one fixed array per device. Host code never
 // uses the array's name as an address: the device address is looked up once
@@ -156,11 +165,12 @@ static void product_noalloc(const hh_handle* h, const void* x, void* y, int64_t 
     d.part = reinterpret_cast<double*>(base + bx + bt);
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (R == 1) {
-        launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, stream);
-        launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(), stream);
+        launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->has_cont, stream);
+        launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(),
+                     h->has_cont, stream);
     } else {
-        launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, stream);
-        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, stream);
+        launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->has_cont, stream);
+        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, h->has_cont, stream);
     }
     HIPCHK(hipGetLastError());
 }
@@ -204,6 +214,8 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
         if (!h) fail(HH_EINVAL, "a handle in the batch is NULL");
         if (!x[t] || !y[t] || x[t] == y[t]) fail(HH_EINVAL, "batch x / y pointers invalid");
         if (h->opt.io_dtype != io) fail(HH_EINVAL, "handles of a batch must share io_dtype");
+        if (h->has_cont != hs[0]->has_cont)
+            fail(HH_ENOTSUP, "a batch cannot mix continuum-stored and fixed-format handles");
         check_device(h);
         for (int u = 0; u < t; ++u)
             if (hs[u] == h) fail(HH_EINVAL, "a handle appears twice in the batch (shared workspace)");
@@ -260,11 +272,12 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
                           (hipStream_t)stream));
     const int R = (int)nrhs;
     launch_gather(descs[0], bp->d_desc, count, bp->max_np, R, stream);
-    launch_dot(descs[0], bp->d_desc, bp->d_dot, bp->ndot, R, stream);
+    const bool cont = hs[0]->has_cont;
+    launch_dot(descs[0], bp->d_desc, bp->d_dot, bp->ndot, R, cont, stream);
     if (R == 1)
-        launch_units(descs[0], bp->d_desc, bp->d_unit, bp->nunit, bp->d_fin, bp->nfin, stream);
+        launch_units(descs[0], bp->d_desc, bp->d_unit, bp->nunit, bp->d_fin, bp->nfin, cont, stream);
     else
-        launch_accumulate(descs[0], bp->d_desc, bp->d_leaf, bp->nleaf, R, stream);
+        launch_accumulate(descs[0], bp->d_desc, bp->d_leaf, bp->nleaf, R, cont, stream);
     HIPCHK(hipGetLastError());
 }
 
@@ -334,6 +347,56 @@ static double decode_cont(const unsigned char* col, int t, int64_t i) {
     for (int b = 0; b < 8; ++b) win |= (uint64_t)col[(bit >> 3) + b] << (8 * b);
     const uint32_t code = (uint32_t)((win >> (bit & 7)) & ((1ull << w) - 1));
     return cont_to_f64(code, t);
+}
+
+void retask(hh_handle* h, int64_t unit_bytes, int64_t dot_task_elems);
+
+// Median milliseconds of one product (HIP events on the stream), after a
+// warm-up product.
+static double time_product(hh_handle* h, const void* x, void* y, void* stream) {
+    product(h, x, y, 1, stream, false);
+    std::vector<double> ms;
+    for (int r = 0; r < 5; ++r) {
+        double ph[3];
+        product(h, x, y, 1, stream, false, ph);
+        ms.push_back(ph[0] + ph[1] + ph[2]);
+    }
+    std::sort(ms.begin(), ms.end());
+    return ms[2];
+}
+
+// Coordinate search over the single-vector task sizes (unit size, then
+// inner-product task size); the handle keeps the fastest tables.
+static void autotune(hh_handle* h, void* stream, hh_tuning* best, hh_tuning* tried, int32_t cap,
+                     int32_t* ntried) {
+    drop_batch_plan(h);
+    const size_t io = h->opt.io_dtype == HH_IO_F32 ? 4 : 8;
+    DevMem tmp;
+    void* x = tmp.alloc((size_t)h->plan.n * io + 256, true);
+    void* y = tmp.alloc((size_t)h->plan.n * io + 256, true);
+    ensure_workspace(h, 1);
+    std::vector<hh_tuning> log;
+    auto trial = [&](int64_t ub, int64_t de) {
+        retask(h, ub, de);
+        hh_tuning t{ub, de, time_product(h, x, y, stream)};
+        log.push_back(t);
+        return t;
+    };
+    hh_tuning b{0, 0, 1e300};
+    for (int64_t ub : {256LL << 10, 512LL << 10, 1LL << 20, 2LL << 20, 4LL << 20}) {
+        const hh_tuning t = trial(ub, 65536);
+        if (t.ms < b.ms) b = t;
+    }
+    for (int64_t de : {16384LL, 32768LL, 131072LL, 262144LL}) {
+        const hh_tuning t = trial(b.unit_bytes, de);
+        if (t.ms < b.ms) b = t;
+    }
+    retask(h, b.unit_bytes, b.dot_task_elems);
+    HIPCHK(hipDeviceSynchronize());
+    *best = b;
+    if (tried)
+        for (size_t i = 0; i < log.size() && (int32_t)i < cap; ++i) tried[i] = log[i];
+    if (ntried) *ntried = (int32_t)log.size();
 }
 
 static double decode(const void* base, int fmt, int64_t i) {
@@ -431,6 +494,26 @@ hh_status hh_matvec_noalloc(const hh_handle* h, const void* x, void* y, int64_t 
                             void* stream) {
     GUARD_BEGIN
     product_noalloc(h, x, y, nrhs, trans != 0, stream);
+    GUARD_END
+}
+
+hh_status hh_solve(const hh_handle* h, const void* b, void* x, double shift, double rtol,
+                   int restart, int max_iter, int trans, int32_t* iters, double* relres,
+                   void* stream) {
+    GUARD_BEGIN
+    if (h) check_device(h);
+    gmres(h, static_cast<const double*>(b), static_cast<double*>(x), shift, rtol, restart, max_iter,
+          trans, iters, relres, stream);
+    GUARD_END
+}
+
+hh_status hh_autotune(hh_handle* h, void* stream, hh_tuning* best, hh_tuning* tried, int32_t cap,
+                      int32_t* ntried) {
+    GUARD_BEGIN
+    if (!h || !best) fail(HH_EINVAL, "handle and best must not be NULL");
+    if (tried && cap < 0) fail(HH_EINVAL, "cap must be >= 0");
+    check_device(h);
+    autotune(h, stream, best, tried, cap, ntried);
     GUARD_END
 }
 

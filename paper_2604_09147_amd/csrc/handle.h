@@ -64,7 +64,12 @@ struct hh_handle {
     int64_t ws_R = 0;
     double* part = nullptr;           // partial rows of the work units (both directions)
     int64_t part_rows = 0;
+    int64_t part_cap = 0;             // rows the part buffer holds
+    // task-table parameters (hh_options / hh_autotune)
+    int64_t unit_bytes = 0;           // factor bytes per single-vector work unit
+    int64_t dot_task_elems = 0;       // stored elements per single-vector phase-V task
     // fp64 factors kept when every low-rank block is stored in fp64
     bool all_fp64 = false;
+    bool has_cont = false;            // some block stored in the continuum format
     hh_stats stats{};
 };

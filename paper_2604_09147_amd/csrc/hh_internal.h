@@ -163,14 +163,15 @@ struct BlockRec {
 // Columns per several-RHS phase-V tile: DOTM_MT MFMA tiles of 16 columns.
 constexpr int DOTM_MT = 1;
 
-// Kernel launch wrappers (defined in the .hip files).
+// Kernel launch wrappers (defined in the .hip files). cont: the handle (or
+// some handle of the batch) stores continuum blocks.
 void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int R, void* stream);
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
-                int R, void* stream);
+                int R, bool cont, void* stream);
 void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
-                       int R, void* stream);
+                       int R, bool cont, void* stream);
 void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,
-                  const FinishTask* fin, int64_t nfin, void* stream);
+                  const FinishTask* fin, int64_t nfin, bool cont, void* stream);
 
 }  // namespace hh
 

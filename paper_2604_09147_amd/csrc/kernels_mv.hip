@@ -328,7 +328,8 @@ __device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs,
 template <int W, int UR>
 __device__ void dot_cont(const DotTask& t, const double* xg, const double* xs, bool lds,
                          double* tb, int wave, int lane) {
-    constexpr int UC = 8 / UR;
+    constexpr int NL = W > 24 ? 4 : 8;             // loads in flight (5-dword loads above 24 bits)
+    constexpr int UC = NL / UR > 0 ? NL / UR : 1;
     const int P = t.P;
     const uint32_t cb = (uint32_t)cont_col_bytes(P, W);
     const rsrc_t rs = make_rsrc(t.col0, (int64_t)t.ncols * cb);
@@ -397,7 +398,11 @@ struct DotCont {
     }
 };
 
-template <int NU, int XL>
+// CONT: the variant for handles with continuum storage, whose low-rank blocks
+// are continuum or fp64 (a launch never mixes them with the 32- and 16-bit
+// formats); the other keeps only the fixed formats, so neither pays the
+// other's registers.
+template <int NU, int XL, bool CONT>
 __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks) {
     __shared__ double xs[XL];
     const DotTask t = ldrec<DotTask>(tasks + blockIdx.x);
@@ -409,21 +414,26 @@ __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks
         for (int i = threadIdx.x; i < t.P; i += 256) xs[i] = ldg<double>(x + i);
         __syncthreads();
     }
-    switch (t.fmt) {
-        case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-        case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-        case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-        case HH_FMT_BF16: dot_r1_any<HH_FMT_BF16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-        default: with_width(t.w, DotCont{t, x, xs, lds, D.tb, wave, lane}); break;
+    if constexpr (CONT) {
+        if (t.fmt == HH_FMT_CONT) with_width(t.w, DotCont{t, x, xs, lds, D.tb, wave, lane});
+        else dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane);
+    } else {
+        switch (t.fmt) {
+            case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+            case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+            case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+            default: dot_r1_any<HH_FMT_BF16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+        }
     }
 }
 
-#define HH_DOT1_KERNEL(NAME, NU, XL, W)                                                         \
+#define HH_DOT1_KERNEL(NAME, NU, XL, W, CONT)                                                   \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void NAME(         \
         Desc d, const Desc* descs, const DotTask* tasks) {                                      \
-        dot1_body<NU, XL>(d, descs, tasks);                                                     \
+        dot1_body<NU, XL, CONT>(d, descs, tasks);                                               \
     }
-HH_DOT1_KERNEL(dot1_kernel, 8, 4096, 4)
+HH_DOT1_KERNEL(dot1_kernel, 8, 4096, 4, false)
+HH_DOT1_KERNEL(dot1c_kernel, 8, 4096, 4, true)
 
 // -------------------------------------------------------------- accumulate
 // Apply one run to a lane's 4 rows: acc += 2^e sum_c col_c[rows] coef_c
@@ -597,7 +607,7 @@ __device__ inline void apply_run_cont(const Run& rn, rsrc_t rs, uint32_t off, ui
     const int n = rn.ncols;
     const int step = SPLIT ? G : 1;
     int c = SPLIT ? g : 0;
-    constexpr int U = 8;
+    constexpr int U = SPLIT || W > 24 ? 4 : 8;
     for (; c + (U - 1) * step < n; c += U * step) {
         CRaw<W> raw[U];
         double cf[U];
@@ -662,18 +672,21 @@ __device__ inline void unit_runs_cont(const Desc& D, const UnitTask& ut, int b, 
     }
 }
 
-template <bool SPLIT, int UB>
+template <bool SPLIT, int UB, bool CONT>
 __device__ inline void unit_runs(const Desc& D, const UnitTask& ut, int64_t row, int g, int G,
                                  double acc[4][1], bool pipe) {
     unit_runs_fmt<HH_FMT_FP64, SPLIT, UB>(D, ut, ut.rb, ut.fe[0], row, g, G, acc, pipe);
-    unit_runs_fmt<HH_FMT_FP32, SPLIT, UB>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc, pipe);
-    unit_runs_fmt<HH_FMT_FP16, SPLIT, UB>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc, pipe);
-    unit_runs_fmt<HH_FMT_BF16, SPLIT, UB>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc, pipe);
-    if (ut.fe[4] > ut.fe[3]) unit_runs_cont<SPLIT>(D, ut, ut.fe[3], ut.fe[4], row, g, G, acc);
+    if constexpr (CONT) {
+        unit_runs_cont<SPLIT>(D, ut, ut.fe[3], ut.fe[4], row, g, G, acc);
+    } else {
+        unit_runs_fmt<HH_FMT_FP32, SPLIT, UB>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc, pipe);
+        unit_runs_fmt<HH_FMT_FP16, SPLIT, UB>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc, pipe);
+        unit_runs_fmt<HH_FMT_BF16, SPLIT, UB>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc, pipe);
+    }
 }
 
 // Four units per workgroup, one per wave; the waves never synchronise.
-template <int UB, bool PIPE>
+template <int UB, bool PIPE, bool CONT>
 __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int64_t ui = (int64_t)blockIdx.x * 4 + wave;
@@ -694,8 +707,8 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
         const int prow = jlo + 4 * sl;
         const int64_t row = prow < P ? prow : 0;     // clamped: in bounds, never written
         double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
-        if (G == 1) unit_runs<false, UB>(D, ut, row, 0, 1, acc, PIPE);
-        else unit_runs<true, UB>(D, ut, row, g, G, acc, PIPE);
+        if (G == 1) unit_runs<false, UB, CONT>(D, ut, row, 0, 1, acc, PIPE);
+        else unit_runs<true, UB, CONT>(D, ut, row, g, G, acc, PIPE);
         for (int off = lps; off < 64; off <<= 1)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q][0] += __shfl_xor(acc[q][0], off, 64);
@@ -707,12 +720,13 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
     }
 }
 
-#define HH_UNIT_KERNEL(NAME, UB, W, PIPE)                                                    \
+#define HH_UNIT_KERNEL(NAME, UB, W, PIPE, CONT)                                              \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void NAME(         \
         Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {                    \
-        unit_body<UB, PIPE>(d, descs, units, nunits);                                           \
+        unit_body<UB, PIPE, CONT>(d, descs, units, nunits);                                     \
     }
-HH_UNIT_KERNEL(unit_kernel, 16, 4, true)
+HH_UNIT_KERNEL(unit_kernel, 16, 4, true, false)
+HH_UNIT_KERNEL(unitc_kernel, 16, 4, true, true)
 
 // y rows of one leaf: its units' partials in unit order, written in caller
 // order. Lane l owns rows 4l..4l+3 of each 256-row strip.
@@ -912,7 +926,7 @@ struct DotmCont {
 
 // Tiles x right-hand-side groups, four per workgroup (one per wave); the groups
 // of one tile are neighbours, so its columns are read from HBM about once.
-template <int NT>
+template <int NT, bool CONT>
 __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, const DotTask* tiles,
                                                    int64_t ntiles, int R, int ngroups) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -922,12 +936,15 @@ __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, co
     const int g = (int)(item - ti * ngroups);
     const DotTask t = ldrec<DotTask>(tiles + ti);
     const Desc D = descs ? ldrec<Desc>(descs + t.hid) : d;
+    if (CONT && t.fmt == HH_FMT_CONT) {
+        if constexpr (CONT) with_width(t.w, DotmCont<NT>{t, D, R, g, lane});
+        return;
+    }
     switch (t.fmt) {
         case HH_FMT_FP64: dotm_tile<HH_FMT_FP64, NT, DOTM_MT>(t, D, R, g, lane); break;
         case HH_FMT_FP32: dotm_tile<HH_FMT_FP32, NT, DOTM_MT>(t, D, R, g, lane); break;
         case HH_FMT_FP16: dotm_tile<HH_FMT_FP16, NT, DOTM_MT>(t, D, R, g, lane); break;
-        case HH_FMT_BF16: dotm_tile<HH_FMT_BF16, NT, DOTM_MT>(t, D, R, g, lane); break;
-        default: with_width(t.w, DotmCont<NT>{t, D, R, g, lane}); break;
+        default: dotm_tile<HH_FMT_BF16, NT, DOTM_MT>(t, D, R, g, lane); break;
     }
 }
 
@@ -1043,7 +1060,7 @@ __device__ inline void accm_runs_cont(const Desc& D, int64_t ci, const LeafTask&
 
 // One workgroup per (leaf, right-hand-side group); wave w owns rows 64 w ..
 // 64 w + 63 of each 256-row strip of the leaf; writes y in caller order.
-template <int NT>
+template <int NT, bool CONT>
 __global__ __launch_bounds__(256) void accm_kernel(Desc d, const Desc* descs, const LeafTask* leaves,
                                                    int R, int ngroups) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -1066,7 +1083,7 @@ __global__ __launch_bounds__(256) void accm_kernel(Desc d, const Desc* descs, co
             accm_runs<HH_FMT_FP32, NT>(D, ci, lt, rowbase, R, g, lane, acc);
             accm_runs<HH_FMT_FP16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
             accm_runs<HH_FMT_BF16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
-            accm_runs_cont<NT>(D, ci, lt, rowbase, R, g, lane, acc);
+            if constexpr (CONT) accm_runs_cont<NT>(D, ci, lt, rowbase, R, g, lane, acc);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -1102,48 +1119,71 @@ void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int
                        descs, R);
 }
 
-void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks, int R,
-                void* stream) {
-    if (ntasks <= 0) return;
-    if (R == 1) {
-        hipLaunchKernelGGL(dot1_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
-                           d, descs, tasks);
-        return;
-    }
-    // several right-hand sides: tasks are tiles of at most 16 columns
+template <bool CONT>
+static void launch_dotm(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
+                        int R, void* stream) {
     const int nt = rhs_tiles_per_group(R);
     const int ngroups = ((R + 15) / 16 + nt - 1) / nt;
     const unsigned grid = (unsigned)((ntasks * ngroups + 3) / 4);
     if (nt == 1)
-        hipLaunchKernelGGL(dotm_kernel<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
-                           tasks, ntasks, R, ngroups);
+        hipLaunchKernelGGL((dotm_kernel<1, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, tasks, ntasks, R, ngroups);
     else if (nt == 2)
-        hipLaunchKernelGGL(dotm_kernel<2>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
-                           tasks, ntasks, R, ngroups);
+        hipLaunchKernelGGL((dotm_kernel<2, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, tasks, ntasks, R, ngroups);
     else
-        hipLaunchKernelGGL(dotm_kernel<4>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
-                           tasks, ntasks, R, ngroups);
+        hipLaunchKernelGGL((dotm_kernel<4, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, tasks, ntasks, R, ngroups);
 }
 
-void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
-                       int R, void* stream) {
-    if (nleaves <= 0) return;
+void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks, int R,
+                bool cont, void* stream) {
+    if (ntasks <= 0) return;
+    if (R == 1) {
+        if (cont)
+            hipLaunchKernelGGL(dot1c_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
+                               d, descs, tasks);
+        else
+            hipLaunchKernelGGL(dot1_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
+                               d, descs, tasks);
+        return;
+    }
+    // several right-hand sides: tasks are tiles of at most 16 columns
+    if (cont) launch_dotm<true>(d, descs, tasks, ntasks, R, stream);
+    else launch_dotm<false>(d, descs, tasks, ntasks, R, stream);
+}
+
+template <bool CONT>
+static void launch_accm(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
+                        int R, void* stream) {
     const int nt = rhs_tiles_per_group_u(R);
     const int ngroups = ((R + 15) / 16 + nt - 1) / nt;
     const unsigned grid = (unsigned)(nleaves * ngroups);
     if (nt == 1)
-        hipLaunchKernelGGL(accm_kernel<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
-                           leaves, R, ngroups);
+        hipLaunchKernelGGL((accm_kernel<1, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, leaves, R, ngroups);
     else
-        hipLaunchKernelGGL(accm_kernel<2>, dim3(grid), dim3(256), 0, (hipStream_t)stream, d, descs,
-                           leaves, R, ngroups);
+        hipLaunchKernelGGL((accm_kernel<2, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, leaves, R, ngroups);
+}
+
+void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
+                       int R, bool cont, void* stream) {
+    if (nleaves <= 0) return;
+    if (cont) launch_accm<true>(d, descs, leaves, nleaves, R, stream);
+    else launch_accm<false>(d, descs, leaves, nleaves, R, stream);
 }
 
 void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,
-                  const FinishTask* fin, int64_t nfin, void* stream) {
-    if (nunits > 0)
-        hipLaunchKernelGGL(unit_kernel, dim3((unsigned)((nunits + 3) / 4)), dim3(256), 0,
-                           (hipStream_t)stream, d, descs, units, nunits);
+                  const FinishTask* fin, int64_t nfin, bool cont, void* stream) {
+    if (nunits > 0) {
+        if (cont)
+            hipLaunchKernelGGL(unitc_kernel, dim3((unsigned)((nunits + 3) / 4)), dim3(256), 0,
+                               (hipStream_t)stream, d, descs, units, nunits);
+        else
+            hipLaunchKernelGGL(unit_kernel, dim3((unsigned)((nunits + 3) / 4)), dim3(256), 0,
+                               (hipStream_t)stream, d, descs, units, nunits);
+    }
     if (nfin > 0)
         hipLaunchKernelGGL(finish_kernel, dim3((unsigned)((nfin + 3) / 4)), dim3(256), 0,
                            (hipStream_t)stream, d, descs, fin, nfin);

@@ -22,7 +22,8 @@ BLK_FAR, BLK_NEAR, BLK_WEAK, BLK_DIAG, BLK_DENSE_NEAR = range(5)
 
 # Exported functions, in the order include/hh.h declares them.
 EXPORTS = ["hh_build", "hh_derive", "hh_switch_level_search", "hh_matvec", "hh_matvec_t",
-           "hh_matvec_timed", "hh_matvec_batch", "hh_matvec_noalloc", "hh_reserve",
+           "hh_matvec_timed", "hh_matvec_batch", "hh_matvec_noalloc", "hh_solve", "hh_autotune",
+           "hh_reserve",
            "hh_get_stats", "hh_block_count", "hh_get_block", "hh_get_block_factors",
            "hh_get_perm", "hh_io_dtype", "hh_size", "hh_free", "hh_plan_create", "hh_plan_info",
            "hh_plan_blocks", "hh_plan_perm", "hh_plan_free", "hh_quantize", "hh_quantize_cont",
@@ -42,7 +43,8 @@ class Kernel(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision_mask", C.c_uint32), ("uniform_fp64", C.c_int), ("io_dtype", C.c_int),
-                ("seed", C.c_uint64), ("continuum", C.c_int)]
+                ("seed", C.c_uint64), ("continuum", C.c_int), ("unit_bytes", C.c_int64),
+                ("dot_task_elems", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -63,6 +65,10 @@ class Stats(C.Structure):
             v = getattr(self, name)
             out[name] = list(v) if isinstance(v, C.Array) else v
         return out
+
+
+class Tuning(C.Structure):
+    _fields_ = [("unit_bytes", C.c_int64), ("dot_task_elems", C.c_int64), ("ms", C.c_double)]
 
 
 class BlockInfo(C.Structure):
@@ -104,6 +110,9 @@ def lib() -> C.CDLL:
         "hh_matvec_batch": ([C.POINTER(_P), C.c_int, C.POINTER(_P), C.POINTER(_P), C.c_int64, _P],
                             C.c_int),
         "hh_matvec_noalloc": ([_P, _P, _P, C.c_int64, C.c_int, _P], C.c_int),
+        "hh_solve": ([_P, _P, _P, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _I32P, _DP, _P],
+                     C.c_int),
+        "hh_autotune": ([_P, _P, C.POINTER(Tuning), C.POINTER(Tuning), C.c_int32, _I32P], C.c_int),
         "hh_reserve": ([_P, C.c_int64], C.c_int),
         "hh_get_stats": ([_P, C.POINTER(Stats)], C.c_int),
         "hh_block_count": ([_P, _I64P], C.c_int),
@@ -191,7 +200,8 @@ def quantize(values, fmt: int, e: int = 0) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ handles
-def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, seed, continuum=False):
+def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, seed, continuum=False,
+                    unit_bytes=0, dot_task_elems=0):
     """hh_kernel and hh_options structs (and the normals array they point to)."""
     nrm = None
     k = Kernel(int(kernel), float(scale), float(h), None)
@@ -199,7 +209,7 @@ def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, see
         nrm = np.ascontiguousarray(normals, dtype=np.float64)
         k.normals = _dptr(nrm)
     o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io_dtype == "f32" else IO_F64,
-                int(seed), int(bool(continuum)))
+                int(seed), int(bool(continuum)), int(unit_bytes), int(dot_task_elems))
     return k, o, nrm
 
 
@@ -255,7 +265,8 @@ class HMatrix:
     def __init__(self, points, kernel: int, tol: float, eta: float, switch_level: int,
                  leaf_size: int, scale: float = 1.0, h: float = 1.0, normals=None,
                  mask: int = 0xF, uniform_fp64: bool = False, io_dtype: str = "f64",
-                 seed: int = 0, continuum: bool = False, _handle=None):
+                 seed: int = 0, continuum: bool = False, unit_bytes: int = 0,
+                 dot_task_elems: int = 0, _handle=None):
         self._h = None
         if _handle is not None:
             self._h = _handle
@@ -263,7 +274,8 @@ class HMatrix:
             pts = np.ascontiguousarray(points, dtype=np.float64)
             n, d = pts.shape
             k, o, self._normals = _kernel_options(kernel, scale, h, normals, mask, uniform_fp64,
-                                                  io_dtype, seed, continuum)
+                                                  io_dtype, seed, continuum, unit_bytes,
+                                                  dot_task_elems)
             _torch_context()
             hp = _P()
             _check(lib().hh_build(_dptr(pts), n, d, C.byref(k), float(tol), float(eta),
@@ -310,6 +322,37 @@ class HMatrix:
         _check(lib().hh_matvec_timed(self._h, C.c_void_p(xc.data_ptr()), C.c_void_p(y.data_ptr()),
                                      nrhs, _stream_ptr(stream, (xc, y)), int(bool(trans)), _dptr(ms)))
         return y, ms
+
+    def solve(self, b, x0=None, shift: float = 0.0, rtol: float = 1e-10, restart: int = 30,
+              max_iter: int = 300, trans: bool = False, stream=None):
+        """Restarted GMRES for (H^ + shift I) x = b (hh_solve): (x, iterations,
+        relative residual)."""
+        import torch
+        if self.io_dtype != "f64":
+            raise TypeError("the solver works on handles with fp64 io")
+        if not b.is_cuda or b.dtype != torch.float64 or b.shape != (self.n,):
+            raise ValueError(f"b must be a float64 device vector of length {self.n}")
+        bc = b.contiguous()
+        x = torch.zeros_like(bc) if x0 is None else x0.detach().clone().contiguous()
+        if x.shape != bc.shape or x.dtype != bc.dtype or not x.is_cuda:
+            raise ValueError("x0 must be shaped like b")
+        it = C.c_int32()
+        rr = C.c_double()
+        _check(lib().hh_solve(self._h, C.c_void_p(bc.data_ptr()), C.c_void_p(x.data_ptr()),
+                              float(shift), float(rtol), int(restart), int(max_iter), int(bool(trans)),
+                              C.byref(it), C.byref(rr), _stream_ptr(stream, (bc, x))))
+        return x, it.value, rr.value
+
+    def autotune(self, stream=None) -> dict:
+        """Task-table sizes picked by measurement (hh_autotune); the handle keeps them."""
+        best = Tuning()
+        tried = (Tuning * 32)()
+        nt = C.c_int32()
+        _check(lib().hh_autotune(self._h, _stream_ptr(stream), C.byref(best), tried, 32, C.byref(nt)))
+        return {"best": {"unit_bytes": best.unit_bytes, "dot_task_elems": best.dot_task_elems,
+                         "ms": best.ms},
+                "tried": [{"unit_bytes": t.unit_bytes, "dot_task_elems": t.dot_task_elems, "ms": t.ms}
+                          for t in tried[:nt.value]]}
 
     def reserve(self, max_nrhs: int) -> None:
         _check(lib().hh_reserve(self._h, int(max_nrhs)))

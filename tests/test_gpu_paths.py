@@ -223,3 +223,27 @@ def test_runs_cut_at_a_lowered_buffer_limit(monkeypatch):
     with pytest.raises(HHError) as ei:
         HMatrix(p.points, p.kernel, tol, p.eta, -1, 48)
     assert ei.value.status == 4
+
+
+def test_autotune_keeps_products_and_picks_a_timed_setting():
+    torch = _torch()
+    from paper_2604_09147_amd import HMatrix
+    rng = np.random.default_rng(12)
+    P = rng.random((20000, 3))
+    g = HMatrix(P, W.INV_R, 1e-6, 1.5, -1, 64)
+    x = torch.from_numpy(rng.standard_normal(20000)).cuda()
+    y0, yt0 = g.matvec(x), g.matvec_t(x)
+    r = g.autotune()
+    assert len(r["tried"]) == 9 and r["best"] in r["tried"]
+    assert r["best"]["ms"] == min(t["ms"] for t in r["tried"])
+    y1, yt1 = g.matvec(x), g.matvec_t(x)
+    # other work units change only the summation order of the leaf rows
+    assert float(torch.linalg.norm(y1 - y0) / torch.linalg.norm(y0)) <= 1e-13
+    assert float(torch.linalg.norm(yt1 - yt0) / torch.linalg.norm(yt0)) <= 1e-13
+    assert torch.equal(y1, g.matvec(x))
+    # a handle built with the chosen sizes gives the tuned handle's products
+    g2 = HMatrix(P, W.INV_R, 1e-6, 1.5, -1, 64, unit_bytes=r["best"]["unit_bytes"],
+                 dot_task_elems=r["best"]["dot_task_elems"])
+    assert torch.equal(g2.matvec(x), y1)
+    g2.free()
+    g.free()
