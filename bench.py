@@ -350,27 +350,31 @@ def main() -> int:
                                "hbm_gbs": s6["matvec_bytes"] / (el_6 / args.steps) / 1e9}
         res["speedup_vs_uniform_fp64"] = el_6 / el_a
         res["adaptive_vs_uniform_rel_diff"] = float(torch.linalg.norm(ya - y6) / torch.linalg.norm(y6))
-        # continuum storage (per block t fraction bits) of the same factors
-        Hc = H64.derive(continuum=True)
-        tune(Hc, "continuum")
-        yc, el_c, med_c, ph_c = run(Hc, x)
-        sc = Hc.stats()
-        bc = Hc.blocks()
-        tb = bc["frac_bits"][bc["format"] == 4]
-        res["continuum"] = {"matvec_per_s": args.steps / el_c, "ms_per_step": 1000 * el_c / args.steps,
-                            "graph_replay_ms_median": round(med_c, 4),
-                            "phase_ms": [round(v, 4) for v in ph_c],
-                            "phase_bytes": [int(v) for v in sc["phase_bytes"]],
-                            "bytes_per_matvec": sc["matvec_bytes"],
-                            "hbm_gbs": sc["matvec_bytes"] / (el_c / args.steps) / 1e9,
-                            "blocks_by_format": sc["blocks_by_format"],
-                            "fraction_bits_histogram": {int(v): int(np.sum(tb == v)) for v in np.unique(tb)},
-                            "speedup_vs_uniform_fp64": el_6 / el_c,
-                            "rel_diff_vs_uniform_fp64": float(torch.linalg.norm(yc - y6) /
-                                                              torch.linalg.norm(y6))}
-        print(f"bench: continuum {1e3 * el_c / args.steps:.3f} ms per product", file=sys.stderr, flush=True)
-        Hc.free()
-        del yc
+        # continuum storage of the same factors: per block t fraction bits, any t
+        # in [7, 23] (continuum) or the byte-aligned t = 7, 15, 23 only
+        for name, mode in (("continuum", 1), ("continuum_aligned", 2)):
+            Hc = H64.derive(continuum=mode)
+            tune(Hc, name)
+            yc, el_c, med_c, ph_c = run(Hc, x)
+            sc = Hc.stats()
+            bc = Hc.blocks()
+            tb = bc["frac_bits"][bc["format"] == 4]
+            res[name] = {"matvec_per_s": args.steps / el_c, "ms_per_step": 1000 * el_c / args.steps,
+                         "graph_replay_ms_median": round(med_c, 4),
+                         "phase_ms": [round(v, 4) for v in ph_c],
+                         "phase_bytes": [int(v) for v in sc["phase_bytes"]],
+                         "bytes_per_matvec": sc["matvec_bytes"],
+                         "hbm_gbs": sc["matvec_bytes"] / (el_c / args.steps) / 1e9,
+                         "blocks_by_format": sc["blocks_by_format"],
+                         "fraction_bits_histogram": {int(v): int(np.sum(tb == v)) for v in np.unique(tb)},
+                         "speedup_vs_uniform_fp64": el_6 / el_c,
+                         "rel_diff_vs_uniform_fp64": float(torch.linalg.norm(yc - y6) /
+                                                           torch.linalg.norm(y6))}
+            print(f"bench: {name} {1e3 * el_c / args.steps:.3f} ms per product", file=sys.stderr,
+                  flush=True)
+            Hc.free()
+            del yc
+            torch.cuda.empty_cache()
         H64.free()
         del y6
         torch.cuda.empty_cache()

@@ -94,7 +94,9 @@ typedef struct {
     int continuum;           /* 1: continuum storage (HH_FMT_CONT) instead of the
                                 mask's formats: each block takes the fewest
                                 fraction bits t in [7, 23] whose unit roundoff
-                                2^-(t+1) passes the rule, else fp64             */
+                                2^-(t+1) passes the rule, else fp64. 2: the same
+                                with t in {7, 15, 23} only (16-, 24- and 32-bit
+                                entries, whole bytes: faster to load)          */
     int64_t unit_bytes;      /* factor bytes per work unit of the single-vector
                                 accumulation; 0 = 1 MiB (hh_autotune picks one)  */
     int64_t dot_task_elems;  /* stored entries per single-vector inner-product

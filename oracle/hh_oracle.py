@@ -68,7 +68,9 @@ R11 continuum storage (the accessor remark of Sec. 4.3, which names no format):
    takes 9 + t bits; t = 7 is bf16 and t = 23 is fp32. A block takes the
    smallest t in [7, 23] whose u passes eq:amp_prec_choice (ties pass), else
    fp64. Rounding stays elementwise relative, so eq:need_mvp and Thm amp hold
-   with the block's u as for the fixed formats.
+   with the block's u as for the fixed formats. The t may also be restricted to
+   a list (cont_ts), e.g. the byte-aligned widths t = 7, 15, 23 (16-, 24- and
+   32-bit entries), with the same rule over that list.
 """
 from __future__ import annotations
 
@@ -666,11 +668,12 @@ def choose_format(nb2: float, total2: float, level: int, d: int, eps: float,
 
 
 def choose_fraction_bits(nb2: float, total2: float, level: int, d: int, eps: float,
-                         tmin: int = CONT_TMIN, tmax: int = CONT_TMAX):
-    """Continuum rule (R11): the smallest t in [tmin, tmax] whose unit roundoff
-    2^-(t+1) passes eq:amp_prec_choice, or None when even tmax fails (fp64)."""
+                         tmin: int = CONT_TMIN, tmax: int = CONT_TMAX, ts=None):
+    """Continuum rule (R11): the smallest t in [tmin, tmax] (or in the list ts)
+    whose unit roundoff 2^-(t+1) passes eq:amp_prec_choice, or None when even
+    the largest fails (fp64)."""
     rhs = (eps * eps) * total2
-    for t in range(tmin, tmax + 1):
+    for t in (range(tmin, tmax + 1) if ts is None else sorted(ts)):
         u = 2.0 ** -(t + 1)
         if ((u * u) * (2.0 ** (d * level))) * nb2 <= rhs:
             return t
@@ -755,7 +758,7 @@ def block_entries(hm_points_tree: np.ndarray, kern: Kernel, normals_tree, b: Blo
 
 def build(points: np.ndarray, kern: Kernel, eps: float, eta: float, switch_level: int,
           leaf_size: int, mask: int = 0xF, uniform: bool = False, seed: int = 0,
-          keep_entries: bool = False, continuum: bool = False) -> HMatrix:
+          keep_entries: bool = False, continuum: bool = False, cont_ts=None) -> HMatrix:
     tree = build_tree(points, leaf_size)
     ell = resolve_switch_level(switch_level, tree.L)
     blocks = partition(tree, eta, switch_level)
@@ -792,7 +795,7 @@ def build(points: np.ndarray, kern: Kernel, eps: float, eta: float, switch_level
         if uniform:
             fmt = FMT_FP64
         elif continuum:
-            tc = choose_fraction_bits(sb.nb2, total2, b.level, tree.d, eps)
+            tc = choose_fraction_bits(sb.nb2, total2, b.level, tree.d, eps, ts=cont_ts)
             fmt, t = (FMT_FP64, -1) if tc is None else (FMT_CONT, tc)
         else:
             fmt = choose_format(sb.nb2, total2, b.level, tree.d, eps, mask)

@@ -25,6 +25,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "handle.h"
@@ -126,8 +127,21 @@ struct Carver {
     }
 };
 
+// Construction resources kept per device between builds: a rocBLAS handle and
+// a scratch buffer of up to 2 GiB (larger scratch is allocated per build and
+// freed after it). Builds in one process run one at a time.
+struct BuildCache {
+    rocblas_handle rb = nullptr;
+    void* scratch = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_build_mu;
+static std::map<int, BuildCache> g_build_cache;
+constexpr size_t CACHED_SCRATCH_MAX = (size_t)2 << 30;
+
 struct Builder {
     hh_handle* h;
+    std::unique_lock<std::mutex> lock{g_build_mu};
     rocblas_handle rb = nullptr;
     hipStream_t st = 0;
     DevMem scratch_mem;
@@ -175,9 +189,7 @@ struct Builder {
     }
 
     explicit Builder(hh_handle* hh) : h(hh), eps2(hh->tol * hh->tol) {}
-    ~Builder() {
-        if (rb) rocblas_destroy_handle(rb);
-    }
+    ~Builder() = default;          // the rocBLAS handle stays in the per-device cache
 
     template <class T>
     T* meta(const std::vector<T>& v, Carver& cv) {
@@ -186,16 +198,49 @@ struct Builder {
         return d;
     }
 
+    // Scratch of one batch of every candidate block at once (an upper bound of
+    // what the batched compression can use).
+    size_t scratch_need() const {
+        double need = 0.0;
+        for (const auto& r : h->blocks) {
+            if (r.b.kind == HH_BLK_DIAG) continue;
+            const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
+            need += std::min(m, n) <= EXACT_SVD_MAX ? (double)exact_item_bytes(m, n)
+                                                    : (double)random_item_bytes(m, n, SKETCH_START);
+        }
+        return need > 1e18 ? (size_t)1 << 60 : (size_t)need;
+    }
+
     void init(size_t cap = (size_t)16 << 30) {
-        RBCHK(rocblas_create_handle(&rb));
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        BuildCache& bc = g_build_cache[dev];
+        if (!bc.rb) RBCHK(rocblas_create_handle(&bc.rb));
+        rb = bc.rb;
         RBCHK(rocblas_set_stream(rb, st));
         size_t freeb = 0, totalb = 0;
         HIPCHK(hipMemGetInfo(&freeb, &totalb));
-        size_t want = freeb / 5;
-        if (want > cap) want = cap;
+        size_t want = std::min<size_t>(freeb / 5, cap);
+        want = std::min(want, scratch_need() + ((size_t)64 << 20));
         if (want < ((size_t)64 << 20)) want = (size_t)64 << 20;
-        scratch_bytes = want;
-        scratch = static_cast<char*>(scratch_mem.alloc(scratch_bytes, false));
+        if (want <= bc.bytes) {
+            scratch = static_cast<char*>(bc.scratch);
+            scratch_bytes = bc.bytes;
+        } else if (want <= CACHED_SCRATCH_MAX) {
+            void* p = nullptr;
+            if (hipMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(HH_ENOMEM, "hipMalloc of the construction scratch failed");
+            }
+            if (bc.scratch) (void)hipFree(bc.scratch);
+            bc.scratch = p;
+            bc.bytes = want;
+            scratch = static_cast<char*>(p);
+            scratch_bytes = want;
+        } else {
+            scratch_bytes = want;
+            scratch = static_cast<char*>(scratch_mem.alloc(scratch_bytes, false));
+        }
     }
 
     // Allocate the fp64 store of a batch and record each block's factor pointers.
@@ -1288,7 +1333,9 @@ static void choose_lowrank_format(const BlockRec& r, double total2, int d, doubl
     const double lhs = std::ldexp(1.0, d * r.b.level) * r.nb2;
     t = 0;
     if (o.continuum) {
-        for (int tt = 7; tt <= 23; ++tt) {
+        // continuum = 2: only the byte-aligned widths 16, 24, 32 (t = 7, 15, 23)
+        const int step = o.continuum == 2 ? 8 : 1;
+        for (int tt = 7; tt <= 23; tt += step) {
             const double u = std::ldexp(1.0, -(tt + 1));
             if ((u * u) * lhs <= rhs) {
                 fmt = HH_FMT_CONT;
@@ -1394,7 +1441,7 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
     if (o.precision_mask == 0) o.precision_mask = 0xF;
     if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
-    if (o.continuum != 0 && o.continuum != 1) fail(HH_EINVAL, "continuum must be 0 or 1");
+    if (o.continuum < 0 || o.continuum > 2) fail(HH_EINVAL, "continuum must be 0, 1 or 2");
     if (o.unit_bytes < 0 || o.dot_task_elems < 0) fail(HH_EINVAL, "task sizes must be >= 0");
 
     // wall time of each stage, printed when HH_VERBOSE is set
@@ -1526,7 +1573,7 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     if (o.precision_mask == 0) o.precision_mask = 0xF;
     if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
-    if (o.continuum != 0 && o.continuum != 1) fail(HH_EINVAL, "continuum must be 0 or 1");
+    if (o.continuum < 0 || o.continuum > 2) fail(HH_EINVAL, "continuum must be 0, 1 or 2");
     if (o.unit_bytes < 0 || o.dot_task_elems < 0) fail(HH_EINVAL, "task sizes must be >= 0");
     if (!src->all_fp64) fail(HH_ENOTSUP, "hh_derive needs a source whose factors are all fp64");
     for (const auto& r : src->blocks)

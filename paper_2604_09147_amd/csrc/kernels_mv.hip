@@ -171,8 +171,14 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadId
 // numbers, widened exactly to fp64.
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
+// Byte-aligned widths (16, 24 and 32 bits: t = 7, 15, 23) put a lane's four
+// entries in whole dwords of their own (2, 3 or 4, at a lane stride of W / 2
+// bytes), so they load without overlap and decode without the funnel shift:
+// the 24-bit entries are byte permutes into the top three bytes of a word.
 template <int W>
-struct CRaw { uint32_t d[W > 24 ? 5 : 4]; };
+constexpr int craw_words() { return W == 16 ? 2 : W == 24 ? 3 : W == 32 ? 4 : W > 24 ? 5 : 4; }
+template <int W>
+struct CRaw { uint32_t d[craw_words<W>()]; };
 
 // Byte offset of the dword holding entry `row` of a column, and the entry's
 // bit offset inside it.
@@ -183,22 +189,50 @@ __device__ inline void cpos(int64_t row, uint32_t& off, uint32_t& sh) {
     sh = (uint32_t)bit & 31u;
 }
 
+typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
+
 template <int W>
 __device__ inline CRaw<W> cload(rsrc_t rs, uint32_t off) {
     CRaw<W> r;
-    const u32x4_t v = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-    r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z; r.d[3] = v.w;
-    if constexpr (W > 24) r.d[4] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 16, 0, 0);
+    if constexpr (W == 16) {
+        const u32x2_t v = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        r.d[0] = v.x; r.d[1] = v.y;
+    } else if constexpr (W == 24) {
+        const u32x3_t v = __builtin_bit_cast(u32x3_t, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
+        r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z;
+    } else {
+        const u32x4_t v = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z; r.d[3] = v.w;
+        if constexpr (W > 24 && W < 32) r.d[4] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 16, 0, 0);
+    }
     return r;
 }
 
 template <int W>
 __device__ inline void cwiden(const CRaw<W>& r, uint32_t sh, double v[4]) {
+    if constexpr (W == 16) {
+        v[0] = (double)__uint_as_float(r.d[0] << 16);
+        v[1] = (double)__uint_as_float(r.d[0] & 0xFFFF0000u);
+        v[2] = (double)__uint_as_float(r.d[1] << 16);
+        v[3] = (double)__uint_as_float(r.d[1] & 0xFFFF0000u);
+        return;
+    } else if constexpr (W == 24) {
+        // entry j = bits [24 j, 24 j + 24); byte 0 of every result is zero
+        v[0] = (double)__uint_as_float(__builtin_amdgcn_perm(r.d[1], r.d[0], 0x0201000Cu));
+        v[1] = (double)__uint_as_float(__builtin_amdgcn_perm(r.d[1], r.d[0], 0x0504030Cu));
+        v[2] = (double)__uint_as_float(__builtin_amdgcn_perm(r.d[2], r.d[1], 0x0403020Cu));
+        v[3] = (double)__uint_as_float(r.d[2] & 0xFFFFFF00u);
+        return;
+    } else if constexpr (W == 32) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (double)__uint_as_float(r.d[j]);
+        return;
+    }
     uint32_t e[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         uint32_t hi = 0u;
-        if constexpr (W > 24) hi = r.d[k + 1];
+        if constexpr (W > 24) hi = r.d[k + 1 < craw_words<W>() ? k + 1 : k];
         else if (k < 3) hi = r.d[k + 1];
         e[k] = __builtin_amdgcn_alignbit(hi, r.d[k], sh);
     }

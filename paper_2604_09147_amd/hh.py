@@ -209,7 +209,7 @@ def _kernel_options(kernel, scale, h, normals, mask, uniform_fp64, io_dtype, see
         nrm = np.ascontiguousarray(normals, dtype=np.float64)
         k.normals = _dptr(nrm)
     o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io_dtype == "f32" else IO_F64,
-                int(seed), int(bool(continuum)), int(unit_bytes), int(dot_task_elems))
+                int(seed), int(continuum), int(unit_bytes), int(dot_task_elems))
     return k, o, nrm
 
 
@@ -265,7 +265,7 @@ class HMatrix:
     def __init__(self, points, kernel: int, tol: float, eta: float, switch_level: int,
                  leaf_size: int, scale: float = 1.0, h: float = 1.0, normals=None,
                  mask: int = 0xF, uniform_fp64: bool = False, io_dtype: str = "f64",
-                 seed: int = 0, continuum: bool = False, unit_bytes: int = 0,
+                 seed: int = 0, continuum: int = 0, unit_bytes: int = 0,
                  dot_task_elems: int = 0, _handle=None):
         self._h = None
         if _handle is not None:
@@ -358,10 +358,10 @@ class HMatrix:
         _check(lib().hh_reserve(self._h, int(max_nrhs)))
 
     def derive(self, mask: int = 0xF, uniform_fp64: bool = False, io_dtype: str | None = None,
-               seed: int = 0, continuum: bool = False) -> "HMatrix":
+               seed: int = 0, continuum: int = 0) -> "HMatrix":
         io = self.io_dtype if io_dtype is None else io_dtype
         o = Options(int(mask), int(bool(uniform_fp64)), IO_F32 if io == "f32" else IO_F64, int(seed),
-                    int(bool(continuum)))
+                    int(continuum))
         hp = _P()
         _check(lib().hh_derive(self._h, C.byref(o), C.byref(hp)))
         return HMatrix(None, 0, 0, 0, 0, 0, _handle=hp)

@@ -28,10 +28,14 @@ def _torch():
     return torch
 
 
-def _pair(P, kind, tol, eta, ell, leaf, normals=None, io="f64"):
+ALIGNED = (7, 15, 23)        # continuum = 2: 16-, 24- and 32-bit entries
+
+
+def _pair(P, kind, tol, eta, ell, leaf, normals=None, io="f64", mode=1):
     from paper_2604_09147_amd import HMatrix
-    g = HMatrix(P, kind, tol, eta, ell, leaf, normals=normals, io_dtype=io, continuum=True)
-    o = O.build(P, O.Kernel(kind, normals=normals), tol, eta, ell, leaf, continuum=True)
+    g = HMatrix(P, kind, tol, eta, ell, leaf, normals=normals, io_dtype=io, continuum=mode)
+    o = O.build(P, O.Kernel(kind, normals=normals), tol, eta, ell, leaf, continuum=True,
+                cont_ts=ALIGNED if mode == 2 else None)
     return g, o
 
 
@@ -58,11 +62,12 @@ def _compare(g, o):
             near = [math.isfinite(t) and abs(t - c.thr) <= w * c.thr for t in (c.tail, c.tail_prev)]
             assert any(near) and abs(int(bl["rank"][q]) - int(st["rank"][q])) == 1, q
         else:
-            # the t decision: u_t^2 2^(d l) ||H~_b||^2 against eps^2 ||H~||^2
+            # the t decision: u_t^2 2^(d l) ||H~_b||^2 against eps^2 ||H~||^2,
+            # at either of the two choices
             w = format_window(sb.rank, min(sb.blk.m, sb.blk.n), len(o.blocks))
-            tt = max(int(bl["frac_bits"][q]), int(t_o[q]), 7)
+            cand = {int(bl["frac_bits"][q]), int(t_o[q])} - {0}
             marg = [((2.0 ** -(u + 1)) ** 2 * 2.0 ** (o.d * sb.blk.level) * sb.nb2) /
-                    (o.eps ** 2 * o.total2) for u in (tt - 1, tt)]
+                    (o.eps ** 2 * o.total2) for u in cand | {u - 1 for u in cand}]
             assert any(abs(m - 1.0) <= w for m in marg), (q, bl["frac_bits"][q], t_o[q], marg)
         ties += 1
     return bl, ties
@@ -87,14 +92,16 @@ def _products(g, o, P, kern, tol, nrhs=1, trans=False, dense=True, io="f64"):
         assert rel(y, yd) <= 10 * tol, rel(y, yd)
 
 
-@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
-def test_continuum_2d_log_against_the_oracle(tol):
+@pytest.mark.parametrize("tol,mode", [(1e-3, 1), (1e-6, 1), (1e-9, 1), (1e-4, 2), (1e-7, 2)])
+def test_continuum_2d_log_against_the_oracle(tol, mode):
     rng = np.random.default_rng(70)
     P = rng.random((3000, 2))
-    g, o = _pair(P, W.LOG, tol, 1.0, -1, 32)
+    g, o = _pair(P, W.LOG, tol, 1.0, -1, 32, mode=mode)
     bl, ties = _compare(g, o)
     widths = set(9 + bl["frac_bits"][bl["format"] == 4])
-    print(f"continuum 2D log tol {tol}: widths {sorted(widths)}, ties {ties}", flush=True)
+    print(f"continuum 2D log tol {tol} mode {mode}: widths {sorted(widths)}, ties {ties}", flush=True)
+    if mode == 2:
+        assert widths <= {16, 24, 32}
     k = O.Kernel(W.LOG)
     for trans in (False, True):
         _products(g, o, P, k, tol, trans=trans)
@@ -120,7 +127,7 @@ def test_continuum_3d_laplace_recipe_and_derived_handle():
     # gives bit for bit the products of the direct build
     h64 = HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, scale=p.scale,
                   uniform_fp64=True)
-    hd = h64.derive(continuum=True)
+    hd = h64.derive(continuum=1)
     bd = hd.blocks()
     assert np.array_equal(bd["frac_bits"], bl["frac_bits"]) and np.array_equal(bd["rank"], bl["rank"])
     x = torch.randn(p.n, dtype=torch.float64, device="cuda")
@@ -128,7 +135,15 @@ def test_continuum_3d_laplace_recipe_and_derived_handle():
     s, s64 = hd.stats(), h64.stats()
     assert s["blocks_by_format"][4] > 0
     assert s["matvec_bytes"] < s64["matvec_bytes"]
-    for h in (g, hd, h64):
+    # the byte-aligned widths, derived, against the oracle's rule over t = 7, 15, 23
+    ha = h64.derive(continuum=2)
+    oa = O.build(p.points, O.Kernel(p.kernel, scale=p.scale), p.tol, p.eta, p.switch_level,
+                 p.leaf_size, continuum=True, cont_ts=ALIGNED)
+    _compare(ha, oa)
+    _products(ha, oa, p.points, k, p.tol)
+    _products(ha, oa, p.points, k, p.tol, trans=True, dense=False)
+    _products(ha, oa, p.points, k, p.tol, nrhs=5, dense=False)
+    for h in (g, hd, h64, ha):
         h.free()
 
 
