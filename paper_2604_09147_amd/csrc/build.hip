@@ -4,7 +4,8 @@
 // the product kernels' tasks.
 //
 // Compression: blocks with min(m, n) <= 512 take the truncated SVD of Sec. 2.2
-// (rocSOLVER's batched SVD of the whole block); larger blocks use a randomized
+// (up to 128 by Householder QR and a one-sided Jacobi SVD of the triangular
+// factor, above by rocSOLVER's batched SVD of the whole block); larger blocks use a randomized
 // range finder (Rademacher sketch keyed by (seed, block, round), one power
 // iteration, width 64 doubling while rank + 16 > width) whose truncation error
 // ||H - Q Q^T H||_F^2 is summed directly, so that every block satisfies
@@ -47,6 +48,7 @@ namespace hh {
     } while (0)
 
 constexpr int EXACT_SVD_MAX = 512;
+constexpr int SMALL_SVD_MAX = 128;         // exact SVD by QR + Jacobi up to here
 constexpr int SKETCH_START = 64;
 constexpr int OVERSAMPLE = 16;
 constexpr int64_t SUM_CHUNK = 65536;
@@ -205,8 +207,10 @@ struct Builder {
         for (const auto& r : h->blocks) {
             if (r.b.kind == HH_BLK_DIAG) continue;
             const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
-            need += std::min(m, n) <= EXACT_SVD_MAX ? (double)exact_item_bytes(m, n)
-                                                    : (double)random_item_bytes(m, n, SKETCH_START);
+            const int64_t p = std::min(m, n);
+            need += p <= SMALL_SVD_MAX   ? (double)exact_small_item_bytes(m, n)
+                    : p <= EXACT_SVD_MAX ? (double)exact_item_bytes(m, n)
+                                         : (double)random_item_bytes(m, n, SKETCH_START);
         }
         return need > 1e18 ? (size_t)1 << 60 : (size_t)need;
     }
@@ -359,6 +363,123 @@ struct Builder {
         HIPCHK(hipGetLastError());
         HIPCHK(hipDeviceSynchronize());
         tock("x.rank+fin");
+    }
+
+    // Exact SVD of blocks with min(m, n) <= SMALL_SVD_MAX without rocSOLVER:
+    // Householder QR of the block (of its transpose when it is wide), then a
+    // one-sided Jacobi SVD of the small triangular factor in LDS / registers.
+    //   tall (M >= N): H = Q R, R^T J = W S  =>  H = (Q J) S W^T: U = Q J, V = W S
+    //   wide (M <  N): H^T = Q R, R J = W S  =>  H = J S (Q W)^T: U = J,   V = Q W S
+    // Zero padding to the batch maximum adds zero singular values only.
+    void exact_small_batch(const std::vector<int64_t>& idx) {
+        const int B = (int)idx.size();
+        int64_t M = 0, N = 0;
+        for (int64_t i : idx) {
+            M = std::max<int64_t>(M, h->blocks[i].b.ie - h->blocks[i].b.ib);
+            N = std::max<int64_t>(N, h->blocks[i].b.je - h->blocks[i].b.jb);
+        }
+        const bool tall = M >= N;
+        const int64_t rows = tall ? M : N;
+        const int s = (int)(tall ? N : M);
+        const int64_t ss = (int64_t)s * s;
+        const int64_t nch = (M * N + SUM_CHUNK - 1) / SUM_CHUNK;
+        Carver cv{scratch, scratch_bytes};
+        double* H = cv.take<double>((size_t)B * M * N);
+        double* Y = tall ? H : cv.take<double>((size_t)B * M * N);
+        double* Q = cv.take<double>((size_t)B * rows * s);
+        double* R = cv.take<double>((size_t)B * ss);
+        double* A = cv.take<double>((size_t)B * ss);
+        double* J = cv.take<double>((size_t)B * ss);
+        double* S = cv.take<double>((size_t)B * s);
+        double* F = cv.take<double>((size_t)B * rows * s);
+        double* nrm = cv.take<double>(B);
+        double* part = cv.take<double>((size_t)B * nch);
+        QrWork qw = qr_work(cv, B, rows, s);
+        std::vector<GenItem> gi(B);
+        std::vector<SumItem> si(B);
+        std::vector<TransItem> ti;
+        for (int b = 0; b < B; ++b) {
+            const Blk& k = h->blocks[idx[b]].b;
+            gi[b] = GenItem{k.ib, k.jb, k.ie - k.ib, k.je - k.jb, H + (int64_t)b * M * N, M, 0, 0};
+            si[b] = SumItem{H + (int64_t)b * M * N, M * N};
+            if (!tall) ti.push_back(TransItem{H + (int64_t)b * M * N, Y + (int64_t)b * M * N, M, N, M, N});
+        }
+        tick();
+        launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, meta(gi, cv), B, M, N, M * N, st);
+        launch_sumsq(meta(si, cv), B, M * N, part, SUM_CHUNK, nrm, st);
+        if (!tall) launch_transpose(meta(ti, cv), B, M * N, st);
+        tock("s.gen");
+        orthq(Y, rows, s, Q, R, qw, B, cv);
+        // Jacobi input: R^T (tall) or R (wide)
+        if (tall) {
+            std::vector<TransItem> tr(B);
+            for (int b = 0; b < B; ++b) tr[b] = TransItem{R + b * ss, A + b * ss, s, s, s, s};
+            launch_transpose(meta(tr, cv), B, ss, st);
+        } else {
+            HIPCHK(hipMemcpyAsync(A, R, (size_t)B * ss * 8, hipMemcpyDeviceToDevice, st));
+        }
+        tock("s.qr");
+        small_svd(A, J, S, B, s, cv);             // A <- W S, J <- rotations
+        const double one = 1.0, zero = 0.0;
+        const rocblas_operation NT = rocblas_operation_none;
+        const rocblas_int ir = (rocblas_int)rows, is = s;
+        // F = Q J (tall: U) or Q A (wide: V)
+        RBCHK(rocblas_dgemm_strided_batched(rb, NT, NT, ir, is, is, &one, Q, ir, rows * s,
+                                            tall ? J : A, is, ss, &zero, F, ir, rows * s, B));
+        std::vector<RankItem> ri(B);
+        for (int b = 0; b < B; ++b) {
+            const Blk& k = h->blocks[idx[b]].b;
+            RankItem r{};
+            r.sigma = S + (int64_t)b * s;
+            r.norm2p = nrm + b;
+            r.extrap = nullptr;
+            r.p = s;
+            r.sketch = 0;
+            r.pmin = (int)std::min(k.ie - k.ib, k.je - k.jb);
+            ri[b] = r;
+        }
+        RankItem* dri = meta(ri, cv);
+        launch_rank(dri, B, eps2, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(ri.data(), dri, B * sizeof(RankItem), hipMemcpyDeviceToHost));
+        std::vector<int> ranks(B);
+        for (int b = 0; b < B; ++b) {
+            record_rank(idx[b], ri[b]);
+            ranks[b] = ri[b].rank;
+        }
+        store_for(idx, ranks);
+        std::vector<FinItem> fi;
+        for (int b = 0; b < B; ++b) {
+            const BlockRec& r = h->blocks[idx[b]];
+            if (!ranks[b]) continue;
+            FinItem f{};
+            f.U = tall ? F + (int64_t)b * rows * s : J + b * ss;
+            f.ldu = tall ? rows : s;
+            f.V = tall ? A + b * ss : F + (int64_t)b * rows * s;
+            f.ldv = tall ? s : rows;
+            f.v_rows = 0;
+            f.sigma = S + (int64_t)b * s;
+            f.Uout = (double*)r.u_ptr;
+            f.Vout = (double*)r.v_ptr;
+            f.ib = r.b.ib;
+            f.jb = r.b.jb;
+            f.PI = r.PI;
+            f.PJ = r.PJ;
+            f.m = (int)(r.b.ie - r.b.ib);
+            f.n = (int)(r.b.je - r.b.jb);
+            f.k = ranks[b];
+            fi.push_back(f);
+        }
+        if (!fi.empty()) launch_finalize(meta(fi, cv), (int)fi.size(), h->d_tpad, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipDeviceSynchronize());
+        tock("s.rank+fin");
+    }
+
+    size_t exact_small_item_bytes(int64_t M, int64_t N) const {
+        const int64_t rows = std::max(M, N), s = std::min(M, N);
+        return 8 * (size_t)(2 * M * N + 2 * rows * s + 4 * s * s + s + 1 + (M * N) / SUM_CHUNK + 1 +
+                            rows * s + 4 * s * s + 64 * s + s) + 8192;
     }
 
     // One block through the non-batched SVD at its exact size, results written
@@ -740,12 +861,18 @@ struct Builder {
     }
 
     void compress(const std::vector<int64_t>& cand) {
-        std::vector<int64_t> exact, rnd;
+        std::vector<int64_t> small, exact, rnd;
         for (int64_t i : cand) {
             const Blk& k = h->blocks[i].b;
-            (std::min(k.ie - k.ib, k.je - k.jb) <= EXACT_SVD_MAX ? exact : rnd).push_back(i);
+            const int64_t p = std::min(k.ie - k.ib, k.je - k.jb);
+            (p <= SMALL_SVD_MAX ? small : p <= EXACT_SVD_MAX ? exact : rnd).push_back(i);
         }
         total_cand = (int64_t)cand.size();
+        batched(small, [&](int64_t M, int64_t N) { return exact_small_item_bytes(M, N); },
+                [&](const std::vector<int64_t>& b) {
+                    exact_small_batch(b);
+                    progress((int64_t)b.size(), "exact SVD (QR + Jacobi)");
+                });
         batched(exact, [&](int64_t M, int64_t N) { return exact_item_bytes(M, N); },
                 [&](const std::vector<int64_t>& b) {
                     exact_batch(b);
