@@ -245,6 +245,68 @@ def switch_level_bench(n: int) -> int:
     return 0
 
 
+def batched_bench(count: int, steps: int, warmup: int) -> int:
+    """Independent Gaussian-kernel instances (N log-uniform in [2^10, 2^16], tol
+    from {1e-4, 1e-6, 1e-8}, h ~ U[0.05, 0.3]), each built on the GPU with its
+    own tree and precision rule, then multiplied together by hh_matvec_batch:
+    one launch per phase over every handle, fp32 x and y."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2604_09147_amd import HMatrix, matvec_batch
+
+    torch.cuda.set_device(0)
+    torch.zeros(1, device="cuda")
+    probs = W.cfg_batched()[:count]
+    t0 = time.perf_counter()
+    hs = []
+    for i, p in enumerate(probs):
+        hs.append(HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, h=p.h,
+                          io_dtype="f32"))
+        if (i + 1) % 32 == 0 or i + 1 == len(probs):
+            print(f"bench: built {i + 1} / {len(probs)} instances, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    t_build = time.perf_counter() - t0
+    rng = np.random.default_rng(4)
+    xs = [torch.from_numpy(rng.standard_normal(h.n)).float().cuda() for h in hs]
+    ys = [torch.empty_like(x) for x in xs]
+    for _ in range(warmup):
+        matvec_batch(hs, xs, ys)
+    # one product of every instance alone, for the bitwise comparison
+    singles = [h.matvec(x) for h, x in zip(hs, xs)]
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(ys, singles))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t1 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        matvec_batch(hs, xs, ys)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    ms = e0.elapsed_time(e1) / steps
+    st = [h.stats() for h in hs]
+    nbytes = float(sum(s["matvec_bytes"] for s in st))
+    fmt = np.sum([s["blocks_by_format"] for s in st], axis=0)
+    out = {"metric": "batched H_h instances: instance-products/s (one launch per phase)",
+           "value": round(count * steps / wall, 1), "unit": "instance-products/s",
+           "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(1e3 * wall / steps, 4),
+           "event_ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 io, f64 accumulation",
+           "data": "synthetic (seeded points uniform in the unit cube, x ~ N(0,1))",
+           "config": {"workload": f"{count} Gaussian-kernel instances exp(-r^2/h^2), N log-uniform "
+                                  "in [2^10, 2^16], tol in {1e-4, 1e-6, 1e-8}, leaf 64, eta sqrt(3)",
+                      "instances": count, "sum_n": int(sum(h.n for h in hs)),
+                      "build_seconds": round(t_build, 2), "parallelism": "1 GPU"},
+           "bytes_per_step": nbytes, "hbm_gbs": round(nbytes / (wall / steps) / 1e9, 1),
+           "blocks_by_format": [int(v) for v in fmt], "batched_equals_single_products": same}
+    print(json.dumps(out), flush=True)
+    for h in hs:
+        h.free()
+    return 0 if same else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +325,9 @@ def main() -> int:
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--switch-level", action="store_true",
                     help="time the switching-level search (Alg. 2) at --n instead")
+    ap.add_argument("--batched", type=int, default=0, metavar="K",
+                    help="time the batched workload instead: the first K of the 512 Gaussian "
+                         "instances, one fp32 RHS each, in one launch per phase")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -274,6 +339,8 @@ def main() -> int:
         return 2
     if args.switch_level:
         return switch_level_bench(args.n)
+    if args.batched:
+        return batched_bench(args.batched, args.steps, args.warmup)
     multi = [int(v) for v in args.multi_rhs.split(",") if v.strip()]
 
     # CPU baseline in a child process, overlapped with the GPU build

@@ -125,9 +125,23 @@ def kernel_entries(kern: Kernel, pi: np.ndarray, pj: np.ndarray,
     gi / gj are the global indices of the points, used to detect the diagonal
     i == j. nj holds the normals of the source points (double layer only)."""
     diff = pi[:, None, :] - pj[None, :, :]
-    r2 = np.sum(diff * diff, axis=2)
-    r = np.sqrt(r2)
     same = gi[:, None] == gj[None, :]
+    return _kernel_values(kern, diff, same, None if nj is None else nj[None, :, :])
+
+
+def kernel_pairs(kern: Kernel, pi: np.ndarray, pj: np.ndarray,
+                 gi: np.ndarray, gj: np.ndarray, nj: np.ndarray | None) -> np.ndarray:
+    """Entries H[gi[k], gj[k]] for paired target points pi (K, d) and source
+    points pj (K, d); nj holds the paired sources' normals (double layer)."""
+    return _kernel_values(kern, pi - pj, gi == gj, nj)
+
+
+def _kernel_values(kern: Kernel, diff: np.ndarray, same: np.ndarray,
+                   nj: np.ndarray | None) -> np.ndarray:
+    """Kernel values from the differences p_i - p_j (last axis = coordinates),
+    the mask of equal indices and the (broadcastable) source normals."""
+    r2 = np.sum(diff * diff, axis=-1)
+    r = np.sqrt(r2)
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         if kern.kind == LOG:
             v = np.log(r)
@@ -140,7 +154,7 @@ def kernel_entries(kern: Kernel, pi: np.ndarray, pj: np.ndarray,
         elif kern.kind == MATERN:
             v = np.exp(-r / kern.h)
         elif kern.kind == DOUBLE_LAYER:
-            num = np.sum(nj[None, :, :] * diff, axis=2)
+            num = np.sum(nj * diff, axis=-1)
             v = num / (r2 * r)
         else:
             raise ValueError(f"unknown kernel {kern.kind}")

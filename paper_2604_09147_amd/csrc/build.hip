@@ -4,8 +4,8 @@
 // the product kernels' tasks.
 //
 // Compression: blocks with min(m, n) <= 512 take the truncated SVD of Sec. 2.2
-// (up to 128 by Householder QR and a one-sided Jacobi SVD of the triangular
-// factor, above by rocSOLVER's batched SVD of the whole block); larger blocks use a randomized
+// (Householder QR of the block, then a one-sided Jacobi SVD of the triangular
+// factor); larger blocks use a randomized
 // range finder (Rademacher sketch keyed by (seed, block, round), one power
 // iteration, width 64 doubling while rank + 16 > width) whose truncation error
 // ||H - Q Q^T H||_F^2 is summed directly, so that every block satisfies
@@ -48,7 +48,8 @@ namespace hh {
     } while (0)
 
 constexpr int EXACT_SVD_MAX = 512;
-constexpr int SMALL_SVD_MAX = 128;         // exact SVD by QR + Jacobi up to here
+constexpr int64_t TSQR_CHUNK = 4096;      // rows of one QR kernel; taller items go through TSQR
+constexpr int JACOBI_TILED_MIN_BATCH = 32;
 constexpr int SKETCH_START = 64;
 constexpr int OVERSAMPLE = 16;
 constexpr int64_t SUM_CHUNK = 65536;
@@ -207,10 +208,8 @@ struct Builder {
         for (const auto& r : h->blocks) {
             if (r.b.kind == HH_BLK_DIAG) continue;
             const int64_t m = r.b.ie - r.b.ib, n = r.b.je - r.b.jb;
-            const int64_t p = std::min(m, n);
-            need += p <= SMALL_SVD_MAX   ? (double)exact_small_item_bytes(m, n)
-                    : p <= EXACT_SVD_MAX ? (double)exact_item_bytes(m, n)
-                                         : (double)random_item_bytes(m, n, SKETCH_START);
+            need += std::min(m, n) <= EXACT_SVD_MAX ? (double)exact_item_bytes(m, n)
+                                                    : (double)random_item_bytes(m, n, SKETCH_START);
         }
         return need > 1e18 ? (size_t)1 << 60 : (size_t)need;
     }
@@ -276,102 +275,13 @@ struct Builder {
         r.fmt = HH_FMT_FP64;
     }
 
-    void exact_batch(const std::vector<int64_t>& idx) {
-        const int B = (int)idx.size();
-        int64_t M = 0, N = 0;
-        for (int64_t i : idx) {
-            M = std::max<int64_t>(M, h->blocks[i].b.ie - h->blocks[i].b.ib);
-            N = std::max<int64_t>(N, h->blocks[i].b.je - h->blocks[i].b.jb);
-        }
-        const int64_t p = std::min(M, N);
-        const int64_t nch = (M * N + SUM_CHUNK - 1) / SUM_CHUNK;
-        Carver cv{scratch, scratch_bytes};
-        double* A = cv.take<double>((size_t)B * M * N);
-        double* U = cv.take<double>((size_t)B * M * p);
-        double* Vt = cv.take<double>((size_t)B * p * N);
-        double* S = cv.take<double>((size_t)B * p);
-        double* E = cv.take<double>((size_t)B * p);
-        double* nrm = cv.take<double>(B);
-        double* part = cv.take<double>((size_t)B * nch);
-        rocblas_int* info = cv.take<rocblas_int>(B);
-        std::vector<GenItem> gi(B);
-        std::vector<SumItem> si(B);
-        std::vector<RankItem> ri(B);
-        for (int b = 0; b < B; ++b) {
-            const Blk& k = h->blocks[idx[b]].b;
-            gi[b] = GenItem{k.ib, k.jb, k.ie - k.ib, k.je - k.jb, A + (int64_t)b * M * N, M, 0, 0};
-            si[b] = SumItem{A + (int64_t)b * M * N, M * N};
-            RankItem r{};
-            r.sigma = S + (int64_t)b * p;
-            r.norm2p = nrm + b;
-            r.extrap = nullptr;
-            r.p = (int)p;
-            r.sketch = 0;
-            r.pmin = (int)std::min(k.ie - k.ib, k.je - k.jb);
-            ri[b] = r;
-        }
-        tick();
-        launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, meta(gi, cv), B, M, N, M * N, st);
-        launch_sumsq(meta(si, cv), B, M * N, part, SUM_CHUNK, nrm, st);
-        tock("x.gen");
-        RBCHK(rocsolver_dgesvd_strided_batched(rb, rocblas_svect_singular, rocblas_svect_singular,
-                                               (rocblas_int)M, (rocblas_int)N, A, (rocblas_int)M,
-                                               M * N, S, p, U, (rocblas_int)M, M * p, Vt,
-                                               (rocblas_int)p, p * N, E, p, rocblas_outofplace,
-                                               info, B));
-        tock("x.gesvd");
-        std::vector<rocblas_int> hinfo(B);
-        HIPCHK(hipMemcpy(hinfo.data(), info, B * sizeof(rocblas_int), hipMemcpyDeviceToHost));
-        // SVDs that did not converge in the padded batch are recomputed alone at
-        // their exact size (U, Vt and S of that item are overwritten in place)
-        for (int b = 0; b < B; ++b)
-            if (hinfo[b] != 0) retry_exact(idx[b], U + (int64_t)b * M * p, M, Vt + (int64_t)b * p * N,
-                                           p, S + (int64_t)b * p, p, hinfo[b], M, N);
-        RankItem* dri = meta(ri, cv);
-        launch_rank(dri, B, eps2, st);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpy(ri.data(), dri, B * sizeof(RankItem), hipMemcpyDeviceToHost));
-        std::vector<int> ranks(B);
-        for (int b = 0; b < B; ++b) {
-            record_rank(idx[b], ri[b]);
-            ranks[b] = ri[b].rank;
-        }
-        store_for(idx, ranks);
-        std::vector<FinItem> fi;
-        for (int b = 0; b < B; ++b) {
-            const BlockRec& r = h->blocks[idx[b]];
-            if (!ranks[b]) continue;
-            FinItem f{};
-            f.U = U + (int64_t)b * M * p;
-            f.V = Vt + (int64_t)b * p * N;
-            f.v_rows = 1;
-            f.sigma = S + (int64_t)b * p;
-            f.Uout = (double*)r.u_ptr;
-            f.Vout = (double*)r.v_ptr;
-            f.ib = r.b.ib;
-            f.jb = r.b.jb;
-            f.ldu = M;
-            f.ldv = p;
-            f.PI = r.PI;
-            f.PJ = r.PJ;
-            f.m = (int)(r.b.ie - r.b.ib);
-            f.n = (int)(r.b.je - r.b.jb);
-            f.k = ranks[b];
-            fi.push_back(f);
-        }
-        if (!fi.empty()) launch_finalize(meta(fi, cv), (int)fi.size(), h->d_tpad, st);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipDeviceSynchronize());
-        tock("x.rank+fin");
-    }
-
-    // Exact SVD of blocks with min(m, n) <= SMALL_SVD_MAX without rocSOLVER:
-    // Householder QR of the block (of its transpose when it is wide), then a
-    // one-sided Jacobi SVD of the small triangular factor in LDS / registers.
+    // Exact SVD of blocks with min(m, n) <= EXACT_SVD_MAX: Householder QR of the
+    // block (of its transpose when it is wide), then a one-sided Jacobi SVD of
+    // the square triangular factor (small_svd).
     //   tall (M >= N): H = Q R, R^T J = W S  =>  H = (Q J) S W^T: U = Q J, V = W S
     //   wide (M <  N): H^T = Q R, R J = W S  =>  H = J S (Q W)^T: U = J,   V = Q W S
     // Zero padding to the batch maximum adds zero singular values only.
-    void exact_small_batch(const std::vector<int64_t>& idx) {
+    void exact_batch(const std::vector<int64_t>& idx) {
         const int B = (int)idx.size();
         int64_t M = 0, N = 0;
         for (int64_t i : idx) {
@@ -476,50 +386,20 @@ struct Builder {
         tock("s.rank+fin");
     }
 
-    size_t exact_small_item_bytes(int64_t M, int64_t N) const {
+    size_t exact_item_bytes(int64_t M, int64_t N) const {
         const int64_t rows = std::max(M, N), s = std::min(M, N);
         return 8 * (size_t)(2 * M * N + 2 * rows * s + 4 * s * s + s + 1 + (M * N) / SUM_CHUNK + 1 +
-                            rows * s + 4 * s * s + 64 * s + s) + 8192;
+                            rows * s + 4 * s * s + 64 * s + s + jacobi_work(s) +
+                            tall_work(rows, s)) + 16384;
     }
-
-    // One block through the non-batched SVD at its exact size, results written
-    // into the batch's output slots (column-major U with ldu, Vt with ldv, S).
-    void retry_exact(int64_t bi, double* Uo, int64_t ldu, double* Vto, int64_t ldv, double* So,
-                     int64_t ps, int first_info, int64_t M, int64_t N) {
-        const Blk& k = h->blocks[bi].b;
-        const int64_t m = k.ie - k.ib, n = k.je - k.jb, p = std::min(m, n);
-        DevMem tmp;
-        double* A = static_cast<double*>(tmp.alloc((size_t)m * n * 8, false));
-        double* U1 = static_cast<double*>(tmp.alloc((size_t)m * p * 8, false));
-        double* V1 = static_cast<double*>(tmp.alloc((size_t)p * n * 8, false));
-        double* S1 = static_cast<double*>(tmp.alloc((size_t)p * 8, false));
-        double* E1 = static_cast<double*>(tmp.alloc((size_t)p * 8 + 8, false));
-        rocblas_int* inf = static_cast<rocblas_int*>(tmp.alloc(64, false));
-        GenItem g{k.ib, k.jb, m, n, A, m, 0, 0};
-        GenItem* dg = static_cast<GenItem*>(tmp.alloc(sizeof(GenItem), false));
-        HIPCHK(hipMemcpy(dg, &g, sizeof(GenItem), hipMemcpyHostToDevice));
-        rocblas_int hi = 1;
-        const rocblas_workmode modes[2] = {rocblas_outofplace, rocblas_inplace};
-        for (int t = 0; t < 2 && hi != 0; ++t) {
-            launch_gen(h->kd, h->d_pts, h->d_nrm, h->d_tpad, dg, 1, m, n, m * n, st);
-            RBCHK(rocsolver_dgesvd(rb, rocblas_svect_singular, rocblas_svect_singular,
-                                   (rocblas_int)m, (rocblas_int)n, A, (rocblas_int)m, S1, U1,
-                                   (rocblas_int)m, V1, (rocblas_int)p, E1, modes[t], inf));
-            HIPCHK(hipMemcpy(&hi, inf, sizeof(hi), hipMemcpyDeviceToHost));
-            if (verbose())
-                fprintf(stderr, "hh: block %lld (%lld x %lld, padded %lld x %lld) batched SVD info %d; "
-                        "alone (mode %d): info %d\n", (long long)bi, (long long)m, (long long)n,
-                        (long long)M, (long long)N, first_info, t, hi);
-        }
-        if (hi != 0)
-            fail(HH_EINTERNAL, "SVD of block " + std::to_string(bi) + " did not converge");
-        HIPCHK(hipMemset(So, 0, ps * 8));
-        HIPCHK(hipMemcpy(So, S1, p * 8, hipMemcpyDeviceToDevice));
-        HIPCHK(hipMemset2D(Uo, ldu * 8, 0, ldu * 8, p));
-        HIPCHK(hipMemcpy2D(Uo, ldu * 8, U1, m * 8, m * 8, p, hipMemcpyDeviceToDevice));
-        HIPCHK(hipMemset2D(Vto, ldv * 8, 0, ldv * 8, N));
-        HIPCHK(hipMemcpy2D(Vto, ldv * 8, V1, p * 8, p * 8, n, hipMemcpyDeviceToDevice));
-        HIPCHK(hipDeviceSynchronize());
+    // doubles of Jacobi workspace per item of width s
+    static int64_t jacobi_work(int64_t s) {
+        // the tiled Jacobi's copy of [A; J] and its preconditioning QR, or
+        // rocSOLVER's three s x s buffers
+        return s > 128 ? std::max<int64_t>(
+                             s <= 512 ? 2 * s * jacobi_tiled_cols((int)s) + 9 * s * s + 70 * s : 0,
+                             3 * s * s + 2 * s + 64)
+                       : 0;
     }
 
     static bool verbose() {
@@ -552,12 +432,13 @@ struct Builder {
         w.W = cv.take<double>((size_t)B * s * s);
         return w;
     }
-    // Householder QR in place (geqrf layout). Up to 64 columns one kernel per
-    // item; wider matrices in 32-column panels whose trailing columns are
-    // updated with the compact-WY form (I - V T V^T)^T through batched GEMMs.
+    // Householder QR in place (geqrf layout). One kernel per item up to 4096
+    // rows (or 64 columns); taller and wider matrices in 32-column panels whose
+    // trailing columns are updated with the compact-WY form (I - V T V^T)^T
+    // through batched GEMMs.
     void house_qr(double* Y, int64_t rows, int s, const QrWork& w, int B) {
         const int64_t strideA = rows * s;
-        if (s <= 64) {
+        if (s <= 64 || rows <= 4096) {
             launch_house_qr(Y, rows, strideA, w.tau, s, rows, s, B, st);
             return;
         }
@@ -601,6 +482,10 @@ struct Builder {
     }
 
     void orthq(double* Y, int64_t rows, int s, double* Q, double* R, const QrWork& w, int B, Carver& cv) {
+        if (rows > TSQR_CHUNK && s <= TSQR_CHUNK / 2) {
+            orthq_tall(Y, rows, s, Q, R, B, cv);
+            return;
+        }
         const double one = 1.0, zero = 0.0, mone = -1.0;
         const rocblas_int ir = (rocblas_int)rows, is = s;
         const int64_t ss = (int64_t)s * s;
@@ -629,9 +514,62 @@ struct Builder {
                                             ir, rows * s, B));
     }
 
+    // Tall items (rows > TSQR_CHUNK): TSQR. The rows are cut into nch chunks of
+    // at most TSQR_CHUNK rows (the last zero-padded: zero rows stay zero in Q),
+    // each chunk is factored as above (one workgroup-sized kernel per chunk),
+    // the chunks' s x s factors stacked ((nch s) x s per item) are factored
+    // once more, and Q = diag(Q_c) Q_stack, i.e. chunk c of Q is Q_c times rows
+    // c s .. c s + s - 1 of Q_stack; R is the stack's factor. The temporaries
+    // are carved after the caller's buffers and released on return.
+    void orthq_tall(double* Y, int64_t rows, int s, double* Q, double* R, int B, Carver& cv) {
+        const size_t mark = cv.off;
+        const int64_t nch = (rows + TSQR_CHUNK - 1) / TSQR_CHUNK;
+        const int64_t ch = (rows + nch - 1) / nch;
+        const int64_t ss = (int64_t)s * s;
+        const int Bc = (int)(B * nch);
+        double* C = cv.take<double>((size_t)Bc * ch * s);
+        double* Qc = cv.take<double>((size_t)Bc * ch * s);
+        double* Rc = cv.take<double>((size_t)Bc * ss);
+        double* S = cv.take<double>((size_t)B * nch * ss);
+        double* Qs = cv.take<double>((size_t)B * nch * ss);
+        std::vector<CopyItem> ci(Bc), si(Bc);
+        for (int b = 0; b < B; ++b)
+            for (int64_t c = 0; c < nch; ++c) {
+                const int64_t r0 = c * ch, m = std::min(ch, rows - r0), k = b * nch + c;
+                ci[k] = CopyItem{Y + (int64_t)b * rows * s + r0, C + k * ch * s, m, s, rows, ch, ch};
+                si[k] = CopyItem{Rc + k * ss, S + (int64_t)b * nch * ss + c * s, s, s, s, nch * s, s};
+            }
+        launch_copy2d(meta(ci, cv), Bc, ch * s, st);
+        QrWork wc = qr_work(cv, Bc, ch, s);
+        orthq(C, ch, s, Qc, Rc, wc, Bc, cv);
+        launch_copy2d(meta(si, cv), Bc, ss, st);
+        QrWork ws = qr_work(cv, B, nch * s, s);
+        orthq(S, nch * s, s, Qs, R, ws, B, cv);
+        const double one = 1.0, zero = 0.0;
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t m = std::min(ch, rows - c * ch);
+            RBCHK(rocblas_dgemm_strided_batched(
+                rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)m, s, s, &one,
+                Qc + c * ch * s, (rocblas_int)ch, nch * ch * s, Qs + c * s, (rocblas_int)(nch * s),
+                nch * ss, &zero, Q + c * ch, (rocblas_int)rows, rows * s, B));
+        }
+        HIPCHK(hipGetLastError());
+        cv.off = mark;
+    }
+    // Scratch doubles per item that orthq_tall adds for a rows x s item.
+    static int64_t tall_work(int64_t rows, int64_t s) {
+        if (rows <= TSQR_CHUNK || s > TSQR_CHUNK / 2) return 0;
+        const int64_t nch = (rows + TSQR_CHUNK - 1) / TSQR_CHUNK;
+        return 3 * (rows + nch) * s + 9 * nch * s * s + 4 * s * s + 70 * nch * s + 64;
+    }
+
     // SVD of the s x s factors R (column-major, stride s^2): A <- U S, J <- V,
-    // sigma decreasing. Jacobi in LDS up to 64; wider sketches use rocSOLVER on
-    // the square matrices (a non-converged item is retried alone in place mode).
+    // sigma decreasing. One-sided Jacobi up to 128 (in LDS up to 64, in
+    // registers up to 128) and, for batches of at least JACOBI_TILED_MIN_BATCH
+    // items, up to 512 (LDS tiles of a global copy: one workgroup per item, so
+    // it pays only when the batch fills the GPU); otherwise rocSOLVER's SVD of
+    // the square matrices (a non-converged item is retried alone in place
+    // mode).
     void small_svd(double* R, double* J, double* S, int B, int s, Carver& cv) {
         const int64_t ss = (int64_t)s * s;
         std::vector<JacItem> ji(B);
@@ -645,6 +583,38 @@ struct Builder {
         if (s <= 128) {
             launch_jacobi128(dj, B, s, st);
             tock("c.jacobi128");
+            return;
+        }
+        if (s <= 512 && B >= JACOBI_TILED_MIN_BATCH) {
+            // Preconditioned: R^T = Q2 R2, then Jacobi on R2^T, whose sweeps
+            // converge several times faster than on R itself (the rows of R2
+            // are graded). R = R2^T Q2^T, so the Jacobi output A = R2^T J is
+            // R's left vectors times S and R's right vectors are Q2 J.
+            const size_t mark = cv.off;
+            double* Rt = cv.take<double>((size_t)B * ss);
+            double* Q2 = cv.take<double>((size_t)B * ss);
+            double* R2 = cv.take<double>((size_t)B * ss);
+            double* J2 = cv.take<double>((size_t)B * ss);
+            std::vector<TransItem> t1(B), t2(B);
+            std::vector<JacItem> jt(B);
+            for (int b = 0; b < B; ++b) {
+                t1[b] = TransItem{R + b * ss, Rt + b * ss, s, s, s, s};
+                t2[b] = TransItem{R2 + b * ss, R + b * ss, s, s, s, s};
+                jt[b] = JacItem{R + b * ss, J2 + b * ss, S + (int64_t)b * s};
+            }
+            launch_transpose(meta(t1, cv), B, ss, st);
+            QrWork w = qr_work(cv, B, s, s);
+            orthq(Rt, s, s, Q2, R2, w, B, cv);
+            launch_transpose(meta(t2, cv), B, ss, st);
+            double* work = cv.take<double>((size_t)B * 2 * s * jacobi_tiled_cols(s));
+            launch_jacobi_tiled(meta(jt, cv), work, B, s, st);
+            const double one = 1.0, zero = 0.0;
+            RBCHK(rocblas_dgemm_strided_batched(rb, rocblas_operation_none, rocblas_operation_none,
+                                                s, s, s, &one, Q2, s, ss, J2, s, ss, &zero, J, s,
+                                                ss, B));
+            HIPCHK(hipGetLastError());
+            cv.off = mark;
+            tock("c.jacobi512");
             return;
         }
         double* Rc = cv.take<double>((size_t)B * ss);
@@ -814,14 +784,10 @@ struct Builder {
         return retry;
     }
 
-    size_t exact_item_bytes(int64_t M, int64_t N) const {
-        int64_t p = std::min(M, N);
-        return 8 * (size_t)(M * N + M * p + p * N + 2 * p + 2 + (M * N) / SUM_CHUNK + 1) + 1024;
-    }
     size_t random_item_bytes(int64_t M, int64_t N, int64_t s) const {
         const int64_t mx = std::max(M, N);
-        return 8 * (size_t)(M * N + 3 * N * s + 2 * M * s + mx * s + 10 * s * s + 64 * s + 4 * s + 3 +
-                            (M * N) / SUM_CHUNK + 1) + 8192;
+        return 8 * (size_t)(M * N + 3 * N * s + 2 * M * s + mx * s + 6 * s * s + 64 * s + 4 * s + 3 +
+                            (M * N) / SUM_CHUNK + 1 + jacobi_work(s) + tall_work(mx, s)) + 16384;
     }
 
     // Size bucket: dimensions within a factor 2^(1/4) share a bucket, so zero
@@ -861,18 +827,12 @@ struct Builder {
     }
 
     void compress(const std::vector<int64_t>& cand) {
-        std::vector<int64_t> small, exact, rnd;
+        std::vector<int64_t> exact, rnd;
         for (int64_t i : cand) {
             const Blk& k = h->blocks[i].b;
-            const int64_t p = std::min(k.ie - k.ib, k.je - k.jb);
-            (p <= SMALL_SVD_MAX ? small : p <= EXACT_SVD_MAX ? exact : rnd).push_back(i);
+            (std::min(k.ie - k.ib, k.je - k.jb) <= EXACT_SVD_MAX ? exact : rnd).push_back(i);
         }
         total_cand = (int64_t)cand.size();
-        batched(small, [&](int64_t M, int64_t N) { return exact_small_item_bytes(M, N); },
-                [&](const std::vector<int64_t>& b) {
-                    exact_small_batch(b);
-                    progress((int64_t)b.size(), "exact SVD (QR + Jacobi)");
-                });
         batched(exact, [&](int64_t M, int64_t N) { return exact_item_bytes(M, N); },
                 [&](const std::vector<int64_t>& b) {
                     exact_batch(b);

@@ -96,6 +96,16 @@ struct TransItem {
     int64_t ld_src, ld_dst;
 };
 
+// Rows [0, rows_dst) of n columns into dst (ld_dst): src rows [0, m) (ld_src),
+// zeros below.
+struct CopyItem {
+    const double* src;
+    double* dst;
+    int64_t m, n;
+    int64_t ld_src, ld_dst;
+    int64_t rows_dst;
+};
+
 struct PackItem {
     const double* src;
     void* dst;
@@ -134,6 +144,7 @@ void launch_finalize(const FinItem* items, int nitems, const int64_t* tpad, hipS
 void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s);
 void launch_pack(const PackItem* items, int nitems, int64_t max_count, hipStream_t s);
 void launch_transpose(const TransItem* items, int nitems, int64_t max_count, hipStream_t s);
+void launch_copy2d(const CopyItem* items, int nitems, int64_t max_count, hipStream_t s);
 void launch_pack_cont(const ContPackItem* items, int nitems, int64_t max_dwords, hipStream_t s);
 void launch_house_qr(double* A, int64_t ld, int64_t strideA, double* tau, int64_t strideT,
                      int64_t m, int n, int nitems, hipStream_t st);
@@ -146,6 +157,10 @@ void launch_qr_extract(const QrItem* items, int nitems, int64_t rows, int s, hip
 void launch_qr_tinv(const QrItem* items, int nitems, int s, hipStream_t st);
 void launch_jacobi(const JacItem* items, int nitems, int s, hipStream_t st);
 void launch_jacobi128(const JacItem* items, int nitems, int s, hipStream_t st);
+// Tiled one-sided Jacobi for 128 < s <= 512; work: nitems x 2 s x jacobi_tiled_cols(s) doubles.
+int jacobi_tiled_width(int s);
+int jacobi_tiled_cols(int s);
+void launch_jacobi_tiled(const JacItem* items, double* work, int nitems, int s, hipStream_t st);
 void launch_svd_to_jac(const JacItem* items, const double* U, const double* Vt, int nitems, int s,
                        hipStream_t st);
 

@@ -375,8 +375,244 @@ __global__ __launch_bounds__(256) void house_qr_kernel(double* A, int64_t ld, in
     }
 }
 
+// Reduce-scatter of NV (a power of two <= 64) values across a wavefront: the
+// first log2(NV) butterfly steps exchange half of the values still held, so
+// that after them each lane keeps one partial sum; the remaining steps add the
+// lanes that hold the same value. Returns the wave total of value
+// lane / (64 / NV). v is consumed.
+template <int C, int NV>
+__device__ inline void rs_step(double (&v)[NV], int lane) {
+    if constexpr (C > 1) {
+        constexpr int half = C / 2;
+        constexpr int off = 32 * C / NV;
+        const bool hi = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = hi ? v[i] : v[i + half];
+            const double keep = hi ? v[i + half] : v[i];
+            v[i] = keep + __shfl_xor(send, off, 64);
+        }
+        rs_step<half, NV>(v, lane);
+    }
+}
+
+template <int NV>
+__device__ inline double wave_rs(double (&v)[NV], int lane) {
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV: power of two <= 64");
+    rs_step<NV, NV>(v, lane);
+    double x = v[0];
+#pragma unroll
+    for (int off = 32 / NV; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Sums of NV per-thread values over a block of NW waves into out[0 .. NV), in
+// a fixed order (wave butterflies, then the waves in order).
+template <int NV, int NW>
+__device__ inline void block_sum(double (&v)[NV], double* red, double* out, int tid) {
+    const int lane = tid & 63, wave = tid >> 6;
+    const double x = wave_rs<NV>(v, lane);
+    constexpr int SH = 64 / NV;
+    if ((lane & (SH - 1)) == 0) red[wave * NV + lane / SH] = x;
+    __syncthreads();
+    if (tid < NV) {
+        double t = red[tid];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t += red[w * NV + tid];
+        out[tid] = t;
+    }
+    __syncthreads();
+}
+
+// The same factorization as house_qr_kernel (geqrf layout, the same reflector
+// definition) for m <= 64 NW RPT rows and n <= m columns. Panels of HQ_PB
+// columns are held in registers (thread t owns rows t + 64 NW q, q < RPT) and
+// factored there; the trailing columns are then updated once per panel with the compact
+// WY form I - V T^T V^T of the panel's reflectors (T upper triangular from
+// V^T V and tau, as in LAPACK's dlarft), HQ_G columns per block reduction.
+constexpr int HQ_PB = 8;
+constexpr int HQ_G = 4;
+constexpr int64_t HOUSE_REG_MAX = 4096;   // rows handled by house_qr_reg_kernel
+template <int RPT, int NW>
+__global__ __launch_bounds__(64 * NW) void house_qr_reg_kernel(double* A, int64_t ld,
+                                                               int64_t strideA, double* tau,
+                                                               int64_t strideT, int m, int n) {
+    constexpr int NTH = 64 * NW;
+    __shared__ double red[NW * 64];
+    __shared__ double out[64];
+    __shared__ double T[HQ_PB * HQ_PB];
+    __shared__ double W2[HQ_PB * HQ_G];
+    __shared__ double tl[HQ_PB];
+    double* a = A + (int64_t)blockIdx.x * strideA;
+    double* tj = tau + (int64_t)blockIdx.x * strideT;
+    const int tid = threadIdx.x;
+    for (int c0 = 0; c0 < n; c0 += HQ_PB) {
+        const int pb = n - c0 < HQ_PB ? n - c0 : HQ_PB;
+        double P[RPT][HQ_PB];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = tid + NTH * q;
+#pragma unroll
+            for (int k = 0; k < HQ_PB; ++k)
+                P[q][k] = (i >= c0 && i < m && k < pb) ? a[(int64_t)(c0 + k) * ld + i] : 0.0;
+        }
+        // factor the panel
+#pragma unroll
+        for (int k = 0; k < HQ_PB; ++k) {
+            if (k >= pb) break;
+            const int j = c0 + k;
+            double s2[2] = {0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + NTH * q;
+                if (i > j && i < m) s2[0] += P[q][k] * P[q][k];
+                if (i == j) s2[1] = P[q][k];
+            }
+            block_sum<2, NW>(s2, red, out, tid);
+            const double sigma = out[0], alpha = out[1];
+            double t = 0.0, beta = alpha, scal = 0.0;
+            if (sigma != 0.0) {
+                const double nrm = sqrt(alpha * alpha + sigma);
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                t = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + NTH * q;
+                if (i > j && i < m && t != 0.0) P[q][k] *= scal;
+                if (i == j) P[q][k] = beta;
+            }
+            if (tid == 0) {
+                tj[j] = t;
+                tl[k] = t;
+            }
+            if (t == 0.0 || k + 1 >= pb) continue;
+            double w[HQ_PB];
+#pragma unroll
+            for (int kk = 0; kk < HQ_PB; ++kk) w[kk] = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + NTH * q;
+                const double vi = i == j ? 1.0 : (i > j && i < m ? P[q][k] : 0.0);
+#pragma unroll
+                for (int kk = k + 1; kk < HQ_PB; ++kk) w[kk] += vi * P[q][kk];
+            }
+            block_sum<HQ_PB, NW>(w, red, out, tid);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + NTH * q;
+                const double vi = i == j ? 1.0 : (i > j && i < m ? P[q][k] : 0.0);
+#pragma unroll
+                for (int kk = k + 1; kk < HQ_PB; ++kk) P[q][kk] -= t * vi * out[kk];
+            }
+        }
+        // write the panel back (rows >= c0) and turn P into the reflectors V
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = tid + NTH * q;
+#pragma unroll
+            for (int k = 0; k < HQ_PB; ++k) {
+                if (i >= c0 && i < m && k < pb) a[(int64_t)(c0 + k) * ld + i] = P[q][k];
+                const int j = c0 + k;
+                P[q][k] = (k < pb && i < m) ? (i == j ? 1.0 : (i > j ? P[q][k] : 0.0)) : 0.0;
+            }
+        }
+        if (c0 + pb >= n) break;
+        // T from the strictly upper part of V^T V (28 pairs)
+        double g[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) g[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            int c = 0;
+#pragma unroll
+            for (int x = 0; x < HQ_PB; ++x)
+#pragma unroll
+                for (int y = x + 1; y < HQ_PB; ++y) g[c++] += P[q][x] * P[q][y];
+        }
+        block_sum<32, NW>(g, red, out, tid);
+        if (tid == 0) {
+            // T[x + HQ_PB y] = T(x, y), upper triangular
+            for (int i = 0; i < HQ_PB * HQ_PB; ++i) T[i] = 0.0;
+            for (int y = 0; y < pb; ++y) {
+                T[y + HQ_PB * y] = tl[y];
+                for (int x = 0; x < y; ++x) {
+                    double z = 0.0;
+                    for (int c = x; c < y; ++c) {
+                        const int gi = c * (2 * HQ_PB - c - 1) / 2 + (y - c - 1);  // pair (c, y)
+                        z += T[x + HQ_PB * c] * out[gi];
+                    }
+                    T[x + HQ_PB * y] = -tl[y] * z;
+                }
+            }
+        }
+        __syncthreads();
+        // trailing columns: C <- C - V (T^T (V^T C))
+        for (int g0 = c0 + pb; g0 < n; g0 += HQ_G) {
+            const int gw = n - g0 < HQ_G ? n - g0 : HQ_G;
+            double wv[HQ_PB * HQ_G];
+#pragma unroll
+            for (int c = 0; c < HQ_PB * HQ_G; ++c) wv[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + NTH * q;
+                if (i < c0 || i >= m) continue;
+#pragma unroll
+                for (int c = 0; c < HQ_G; ++c) {
+                    if (c >= gw) break;
+                    const double x = a[(int64_t)(g0 + c) * ld + i];
+#pragma unroll
+                    for (int y = 0; y < HQ_PB; ++y) wv[y * HQ_G + c] += P[q][y] * x;
+                }
+            }
+            block_sum<HQ_PB * HQ_G, NW>(wv, red, out, tid);
+            if (tid < HQ_PB * HQ_G) {
+                const int y = tid / HQ_G, c = tid % HQ_G;
+                double z = 0.0;
+                for (int x = 0; x <= y; ++x) z += T[x + HQ_PB * y] * out[x * HQ_G + c];
+                W2[tid] = z;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + NTH * q;
+                if (i < c0 || i >= m) continue;
+#pragma unroll
+                for (int c = 0; c < HQ_G; ++c) {
+                    if (c >= gw) break;
+                    double* px = a + (int64_t)(g0 + c) * ld + i;
+                    double x = *px;
+#pragma unroll
+                    for (int y = 0; y < HQ_PB; ++y) x -= P[q][y] * W2[y * HQ_G + c];
+                    *px = x;
+                }
+            }
+        }
+    }
+}
+
 void launch_house_qr(double* A, int64_t ld, int64_t strideA, double* tau, int64_t strideT,
                      int64_t m, int n, int nitems, hipStream_t st) {
+    if (n <= m && m <= HOUSE_REG_MAX) {
+        const int mi = (int)m;
+        if (m <= 256)
+            hipLaunchKernelGGL((house_qr_reg_kernel<1, 4>), dim3(nitems), dim3(256), 0, st, A, ld,
+                               strideA, tau, strideT, mi, n);
+        else if (m <= 512)
+            hipLaunchKernelGGL((house_qr_reg_kernel<2, 4>), dim3(nitems), dim3(256), 0, st, A, ld,
+                               strideA, tau, strideT, mi, n);
+        else if (m <= 1024)
+            hipLaunchKernelGGL((house_qr_reg_kernel<4, 4>), dim3(nitems), dim3(256), 0, st, A, ld,
+                               strideA, tau, strideT, mi, n);
+        else if (m <= 2048)
+            hipLaunchKernelGGL((house_qr_reg_kernel<8, 4>), dim3(nitems), dim3(256), 0, st, A, ld,
+                               strideA, tau, strideT, mi, n);
+        else
+            hipLaunchKernelGGL((house_qr_reg_kernel<8, 8>), dim3(nitems), dim3(512), 0, st, A, ld,
+                               strideA, tau, strideT, mi, n);
+        return;
+    }
     hipLaunchKernelGGL(house_qr_kernel, dim3(nitems), dim3(256), 0, st, A, ld, strideA, tau,
                        strideT, m, n);
 }
@@ -697,6 +933,152 @@ void launch_jacobi128(const JacItem* items, int nitems, int s, hipStream_t st) {
     hipLaunchKernelGGL(jacobi128_kernel, dim3(nitems), dim3(512), 0, st, items, s);
 }
 
+// One-sided Jacobi SVD for 128 < s <= 512 with the matrix in global memory.
+// Each item works on [A; J] (2s rows, sp >= s columns padded with zero columns,
+// column-major in work): the columns form nb = sp / b blocks of b (16 up to
+// s = 256, else 8); a sweep visits every pair of blocks once (round-robin), and
+// each visit loads the two blocks into LDS and rotates every pair of their 2b
+// columns once (round-robin again, one wave per column pair, b waves). Same
+// rotation as the kernels above; a pair is skipped when
+// |a_p^T a_q| <= tol ||a_p|| ||a_q|| with tol = s 2^-53 (the rounding level of
+// an inner product of length s: below it rotations only chase rounding noise),
+// and the sweeps stop when one rotates nothing (at most 40). Zero (padding)
+// columns never rotate. Output sorted as in the kernels above.
+constexpr int JT_TILE = 32 * 528;     // 2b columns x (2s + 16) rows, b s = 4096
+__device__ inline void rr_pair(int n, int round, int k, int& p, int& q) {
+    // circle method for n (even) players: player n - 1 fixed
+    if (k == 0) {
+        p = round;
+        q = n - 1;
+    } else {
+        p = (round + k) % (n - 1);
+        q = (round - k + (n - 1)) % (n - 1);
+    }
+    if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(64 * B) void jacobi_tiled_kernel(const JacItem* items, double* work,
+                                                              int s, int sp) {
+    constexpr int NTH = 64 * B, N2 = 2 * B;
+    __shared__ double tile[JT_TILE];
+    __shared__ double sig[512];
+    __shared__ int order[512];
+    __shared__ int rotated;
+    const JacItem it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int R = 2 * s, ldt = R + 16, nb = sp / B;
+    const int pr = tid >> 6, ln = tid & 63;
+    double* w = work + (int64_t)blockIdx.x * R * sp;
+    for (int64_t idx = tid; idx < (int64_t)R * sp; idx += NTH) {
+        const int i = (int)(idx % R), c = (int)(idx / R);
+        double v = 0.0;
+        if (c < s) v = i < s ? it.A[i + (int64_t)c * s] : (i - s == c ? 1.0 : 0.0);
+        w[idx] = v;
+    }
+    const double tol = (double)s * 0x1p-53;
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int ro = 0; ro < nb - 1; ++ro) {
+            for (int k = 0; k < nb / 2; ++k) {
+                int B1, B2;
+                rr_pair(nb, ro, k, B1, B2);
+                for (int idx = tid; idx < N2 * R; idx += NTH) {
+                    const int i = idx % R, c = idx / R;
+                    const int gc = c < B ? B1 * B + c : B2 * B + (c - B);
+                    tile[c * ldt + i] = w[(int64_t)gc * R + i];
+                }
+                __syncthreads();
+                for (int r = 0; r < N2 - 1; ++r) {
+                    int p, q;
+                    rr_pair(N2, r, pr, p, q);
+                    double* up = tile + p * ldt;
+                    double* uq = tile + q * ldt;
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll 4
+                    for (int i = ln; i < s; i += 64) {
+                        const double x = up[i], y = uq[i];
+                        al += x * x;
+                        be += y * y;
+                        ga += x * y;
+                    }
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) {
+                        al += __shfl_xor(al, off, 64);
+                        be += __shfl_xor(be, off, 64);
+                        ga += __shfl_xor(ga, off, 64);
+                    }
+                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        const double t =
+                            (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll 4
+                        for (int i = ln; i < R; i += 64) {
+                            const double x = up[i], y = uq[i];
+                            up[i] = c * x - sn * y;
+                            uq[i] = sn * x + c * y;
+                        }
+                        if (ln == 0) rotated = 1;
+                    }
+                    __syncthreads();
+                }
+                for (int idx = tid; idx < N2 * R; idx += NTH) {
+                    const int i = idx % R, c = idx / R;
+                    const int gc = c < B ? B1 * B + c : B2 * B + (c - B);
+                    w[(int64_t)gc * R + i] = tile[c * ldt + i];
+                }
+                __syncthreads();
+            }
+        }
+        const int any = rotated;
+        __syncthreads();
+        if (!any) break;
+    }
+    for (int c = tid; c < sp; c += NTH) {
+        double a = 0.0;
+        const double* col = w + (int64_t)c * R;
+        for (int i = 0; i < s; ++i) a += col[i] * col[i];
+        sig[c] = sqrt(a);
+    }
+    __syncthreads();
+    for (int c = tid; c < sp; c += NTH) {
+        int rank = 0;
+        for (int u = 0; u < sp; ++u)
+            if (sig[u] > sig[c] || (sig[u] == sig[c] && u < c)) ++rank;
+        order[rank] = c;
+    }
+    __syncthreads();
+    for (int64_t idx = tid; idx < (int64_t)s * s; idx += NTH) {
+        const int i = (int)(idx % s), r = (int)(idx / s);
+        const double* col = w + (int64_t)order[r] * R;
+        it.A[idx] = col[i];
+        it.J[idx] = col[s + i];
+    }
+    for (int r = tid; r < s; r += NTH) it.sigma[r] = sig[order[r]];
+}
+
+int jacobi_tiled_width(int s) { return s <= 256 ? 16 : 8; }
+int jacobi_tiled_cols(int s) {
+    const int b2 = 2 * jacobi_tiled_width(s);
+    return (s + b2 - 1) / b2 * b2;
+}
+
+void launch_jacobi_tiled(const JacItem* items, double* work, int nitems, int s, hipStream_t st) {
+    if (jacobi_tiled_width(s) == 16)
+        hipLaunchKernelGGL(jacobi_tiled_kernel<16>, dim3(nitems), dim3(1024), 0, st, items, work, s,
+                           jacobi_tiled_cols(s));
+    else
+        hipLaunchKernelGGL(jacobi_tiled_kernel<8>, dim3(nitems), dim3(512), 0, st, items, work, s,
+                           jacobi_tiled_cols(s));
+}
+
 // rocSOLVER SVD R = U S V^T of a square s x s matrix -> the Jacobi outputs:
 // A <- U S (columns sigma_r u_r), J <- V.
 __global__ void svd_to_jac_kernel(const JacItem* items, const double* U, const double* Vt, int s) {
@@ -773,6 +1155,17 @@ __global__ void transpose_kernel(const TransItem* items) {
     }
 }
 
+// dst rows [0, rows_dst) of n columns: src rows [0, m), zeros below.
+__global__ void copy2d_kernel(const CopyItem* items) {
+    const CopyItem it = items[blockIdx.y];
+    const int64_t count = it.rows_dst * it.n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / it.rows_dst, i = e - j * it.rows_dst;
+        it.dst[j * it.ld_dst + i] = i < it.m ? it.src[j * it.ld_src + i] : 0.0;
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
 void launch_gen(const KernelDev& k, const double* pts, const double* nrm, const int64_t* tpad,
@@ -833,6 +1226,11 @@ void launch_maxabs(const SumItem* items, int nitems, double* out, hipStream_t s)
 void launch_transpose(const TransItem* items, int nitems, int64_t max_count, hipStream_t s) {
     dim3 grid(grid_for(max_count, 4096), nitems);
     hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, items);
+}
+
+void launch_copy2d(const CopyItem* items, int nitems, int64_t max_count, hipStream_t s) {
+    dim3 grid(grid_for(max_count, 4096), nitems);
+    hipLaunchKernelGGL(copy2d_kernel, grid, dim3(256), 0, s, items);
 }
 
 void launch_pack_cont(const ContPackItem* items, int nitems, int64_t max_dwords, hipStream_t s) {
