@@ -82,20 +82,29 @@ __device__ inline const void* elem_ptr(const void* base, int64_t i) {
     else return static_cast<const uint16_t*>(base) + i;
 }
 
-// Elements i .. i+3 (i a multiple of 4, so the access is aligned).
-template <int FMT>
+// A global load marked non-temporal: factor data is read once per product, so
+// it should not displace the vectors and coefficients held in the caches.
+template <class T>
+__device__ inline T ldg_nt(const void* p) {
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+}
+
+// Elements i .. i+3 (i a multiple of 4, so the access is aligned); NT: a
+// non-temporal load.
+template <int FMT, bool NT = false>
 __device__ inline Raw4<FMT> load4(const void* base, int64_t i) {
     Raw4<FMT> r;
     const void* p = elem_ptr<FMT>(base, i);
     if constexpr (FMT == HH_FMT_FP64) {
-        r.a = ldg<dbl2_t>(p);
-        r.b = ldg<dbl2_t>(static_cast<const dbl2_t*>(p) + 1);
+        r.a = NT ? ldg_nt<dbl2_t>(p) : ldg<dbl2_t>(p);
+        r.b = NT ? ldg_nt<dbl2_t>(static_cast<const dbl2_t*>(p) + 1)
+                 : ldg<dbl2_t>(static_cast<const dbl2_t*>(p) + 1);
     } else if constexpr (FMT == HH_FMT_FP32) {
-        r.a = ldg<flt4_t>(p);
+        r.a = NT ? ldg_nt<flt4_t>(p) : ldg<flt4_t>(p);
     } else if constexpr (FMT == HH_FMT_FP16) {
-        r.a = ldg<half4_t>(p);
+        r.a = NT ? ldg_nt<half4_t>(p) : ldg<half4_t>(p);
     } else {
-        r.a = ldg<u32x2_t>(p);
+        r.a = NT ? ldg_nt<u32x2_t>(p) : ldg<u32x2_t>(p);
     }
     return r;
 }
@@ -111,19 +120,26 @@ __device__ inline rsrc_t make_rsrc(const void* base, int64_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, RSRC_WORD3);
 }
 
+// Cache policy of a buffer load: CP_STREAM marks it non-temporal (the
+// single-vector kernels read every factor byte once per product; measured at
+// the benchmark size, the product is 6% faster with it). The several-RHS
+// kernels keep the default policy: their right-hand-side groups re-read a
+// tile's columns from L2.
+constexpr int CP_STREAM = 2;
+
 // Elements at byte offset off .. off + 4 elements of a buffer.
-template <int FMT>
+template <int FMT, int CP = 0>
 __device__ inline Raw4<FMT> bload4(rsrc_t rs, uint32_t off) {
     Raw4<FMT> r;
     if constexpr (FMT == HH_FMT_FP64) {
-        r.a = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-        r.b = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+        r.a = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, CP));
+        r.b = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, CP));
     } else if constexpr (FMT == HH_FMT_FP32) {
-        r.a = __builtin_bit_cast(flt4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        r.a = __builtin_bit_cast(flt4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, CP));
     } else if constexpr (FMT == HH_FMT_FP16) {
-        r.a = __builtin_bit_cast(half4_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        r.a = __builtin_bit_cast(half4_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, CP));
     } else {
-        r.a = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        r.a = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, CP));
     }
     return r;
 }
@@ -191,19 +207,19 @@ __device__ inline void cpos(int64_t row, uint32_t& off, uint32_t& sh) {
 
 typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
 
-template <int W>
+template <int W, int CP = 0>
 __device__ inline CRaw<W> cload(rsrc_t rs, uint32_t off) {
     CRaw<W> r;
     if constexpr (W == 16) {
-        const u32x2_t v = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        const u32x2_t v = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, CP));
         r.d[0] = v.x; r.d[1] = v.y;
     } else if constexpr (W == 24) {
-        const u32x3_t v = __builtin_bit_cast(u32x3_t, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
+        const u32x3_t v = __builtin_bit_cast(u32x3_t, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, CP));
         r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z;
     } else {
-        const u32x4_t v = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        const u32x4_t v = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, CP));
         r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z; r.d[3] = v.w;
-        if constexpr (W > 24 && W < 32) r.d[4] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 16, 0, 0);
+        if constexpr (W > 24 && W < 32) r.d[4] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 16, 0, CP);
     }
     return r;
 }
@@ -309,7 +325,7 @@ __device__ void dot_r1(const DotTask& t, const double* xg, const double* xs, boo
 #pragma unroll
                 for (int ur = 0; ur < UR; ++ur) {
                     const int r = rb + 256 * ur + 4 * lane;
-                    raw[uc][ur] = load4<FMT>(t.col0, (int64_t)c * P + (r < P ? r : 0));
+                    raw[uc][ur] = load4<FMT, true>(t.col0, (int64_t)c * P + (r < P ? r : 0));
                 }
             }
 #pragma unroll
@@ -360,8 +376,8 @@ __device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs,
 // Continuum columns: UC columns x UR pieces of 256 rows per wave iteration,
 // fp64 accumulation, the per-lane bit position computed once per piece.
 template <int W, int UR>
-__device__ void dot_cont(const DotTask& t, const double* xg, const double* xs, bool lds,
-                         double* tb, int wave, int lane) {
+__device__ __forceinline__ void dot_cont(const DotTask& t, const double* xg, const double* xs,
+                                         bool lds, double* tb, int wave, int lane) {
     constexpr int NL = W > 24 ? 4 : 8;             // loads in flight (5-dword loads above 24 bits)
     constexpr int UC = NL / UR > 0 ? NL / UR : 1;
     const int P = t.P;
@@ -382,7 +398,7 @@ __device__ void dot_cont(const DotTask& t, const double* xg, const double* xs, b
 #pragma unroll
                 for (int uc = 0; uc < UC; ++uc) {
                     const int c = c0 + uc < t.ncols ? c0 + uc : t.ncols - 1;
-                    raw[uc][ur] = cload<W>(rs, off + (uint32_t)c * cb);
+                    raw[uc][ur] = cload<W, CP_STREAM>(rs, off + (uint32_t)c * cb);
                 }
             }
 #pragma unroll
@@ -416,14 +432,14 @@ __device__ void dot_cont(const DotTask& t, const double* xg, const double* xs, b
 }
 
 struct DotCont {
-    const DotTask& t;
+    DotTask t;
     const double* xg;
     const double* xs;
     bool lds;
     double* tb;
     int wave, lane;
     template <int W>
-    __device__ void operator()() const {
+    __device__ __forceinline__ void operator()() const {
         const int nb = (t.P + 255) / 256;
         if (!lds && nb > 1) dot_cont<W, 2>(t, xg, xs, lds, tb, wave, lane);
         else if (nb <= 1) dot_cont<W, 1>(t, xg, xs, lds, tb, wave, lane);
@@ -488,7 +504,7 @@ __device__ inline void apply_cols(const Run& rn, rsrc_t rs, uint32_t voff, const
     for (int u = 0; u < UB; ++u) {
         const int cu = c + u * step;
         const int cc = CLAMP ? (cu < n ? cu : n - 1) : cu;
-        raw[u] = bload4<FMT>(rs, voff + (uint32_t)cc * (uint32_t)rn.stride * elem_bytes<FMT>());
+        raw[u] = bload4<FMT, CP_STREAM>(rs, voff + (uint32_t)cc * (uint32_t)rn.stride * elem_bytes<FMT>());
         const double* cp = coef + ((int64_t)rn.toff + cc) * R + r0;
 #pragma unroll
         for (int k = 0; k < RC; ++k) {
@@ -555,7 +571,7 @@ __device__ inline void apply_run_pipe(const Run& rn, rsrc_t rs, uint32_t voff, c
         double cfc[UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
-            cur[u] = bload4<FMT>(rs, voff + (uint32_t)u * cstep);
+            cur[u] = bload4<FMT, CP_STREAM>(rs, voff + (uint32_t)u * cstep);
             cfc[u] = ldc<double>(coef + rn.toff + u);
         }
         for (int b = 1; b < nb; ++b) {
@@ -564,7 +580,7 @@ __device__ inline void apply_run_pipe(const Run& rn, rsrc_t rs, uint32_t voff, c
 #pragma unroll
             for (int u = 0; u < UP; ++u) {
                 const int c = b * UP + u;
-                nxt[u] = bload4<FMT>(rs, voff + (uint32_t)c * cstep);
+                nxt[u] = bload4<FMT, CP_STREAM>(rs, voff + (uint32_t)c * cstep);
                 cfn[u] = ldc<double>(coef + rn.toff + c);
             }
 #pragma unroll
@@ -648,7 +664,7 @@ __device__ inline void apply_run_cont(const Run& rn, rsrc_t rs, uint32_t off, ui
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int cc = c + u * step;
-            raw[u] = cload<W>(rs, off + (uint32_t)cc * cb);
+            raw[u] = cload<W, CP_STREAM>(rs, off + (uint32_t)cc * cb);
             cf[u] = SPLIT ? ldg<double>(coef + rn.toff + cc) : ldc<double>(coef + rn.toff + cc);
         }
 #pragma unroll
@@ -666,7 +682,7 @@ __device__ inline void apply_run_cont(const Run& rn, rsrc_t rs, uint32_t off, ui
         for (int u = 0; u < 4; ++u) {
             const int cu = c + u * step;
             const int cc = cu < n ? cu : n - 1;
-            raw[u] = cload<W>(rs, off + (uint32_t)cc * cb);
+            raw[u] = cload<W, CP_STREAM>(rs, off + (uint32_t)cc * cb);
             const double w = SPLIT ? ldg<double>(coef + rn.toff + cc) : ldc<double>(coef + rn.toff + cc);
             cf[u] = cu < n ? w : 0.0;
         }
@@ -682,7 +698,7 @@ __device__ inline void apply_run_cont(const Run& rn, rsrc_t rs, uint32_t off, ui
 
 template <bool SPLIT>
 struct RunCont {
-    const Run& rn;
+    Run rn;
     rsrc_t rs;
     int64_t crow;            // first row of the lane inside the cluster's columns
     const double* coef;
@@ -951,8 +967,8 @@ __device__ void dotm_tile_cont(const DotTask& t, const Desc& D, int R, int g, in
 
 template <int NT>
 struct DotmCont {
-    const DotTask& t;
-    const Desc& D;
+    DotTask t;
+    Desc D;
     int R, g, lane;
     template <int W>
     __device__ void operator()() const { dotm_tile_cont<W, NT, DOTM_MT>(t, D, R, g, lane); }
@@ -1069,7 +1085,7 @@ __device__ inline void accm_run_cont(const Run& rn, const double* tb, int64_t cr
 
 template <int NT>
 struct AccmCont {
-    const Run& rn;
+    Run rn;
     const double* tb;
     int64_t crow;
     int R, g, lane;

@@ -67,6 +67,7 @@ def _dense_rows(points, kern, x, rows, trans, rho, chunk=64):
     x2 = x.reshape(n, -1)
     out = np.zeros((rows.size, x2.shape[1]))
     far2 = np.zeros(rows.size)
+    sq = np.sum(points * points, axis=1)
     for a in range(0, rows.size, chunk):
         r = rows[a:a + chunk]
         if trans:
@@ -75,7 +76,9 @@ def _dense_rows(points, kern, x, rows, trans, rho, chunk=64):
         else:
             blk = O.kernel_entries(kern, points[r], points, r, g, kern.normals)
         out[a:a + chunk] = blk @ x2
-        d2 = np.sum((points[r][:, None, :] - points[None, :, :]) ** 2, axis=2)
+        # squared distances through the Gram expansion (only compared with rho^2;
+        # a pair within rounding of rho changes the sum by one bounded term)
+        d2 = sq[r][:, None] + sq[None, :] - 2.0 * (points[r] @ points.T)
         far2[a:a + chunk] = np.sum(np.where(d2 > rho * rho, blk * blk, 0.0), axis=1)
     return out.reshape((rows.size,) + x.shape[1:]), far2
 
