@@ -320,6 +320,10 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default task sizes instead of the tuned ones")
     ap.add_argument("--no-uniform", action="store_true", help="build the adaptive handle only")
+    ap.add_argument("--unit-bytes", type=int, default=0,
+                    help="with --dot-task-elems: fixed task sizes for the adaptive handle "
+                         "instead of the autotuner's (to profile a tuned configuration)")
+    ap.add_argument("--dot-task-elems", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -365,8 +369,13 @@ def main() -> int:
     print(f"bench: building {p.name} N={p.n} leaf={p.leaf_size} eta={p.eta} "
           f"switch={p.switch_level} tol={p.tol}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
+    fixed_sizes = bool(args.unit_bytes and args.dot_task_elems)
+    if fixed_sizes and not args.no_uniform:
+        print("--unit-bytes / --dot-task-elems need --no-uniform", file=sys.stderr)
+        return 2
     if args.no_uniform:
-        Ha = HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, scale=p.scale)
+        Ha = HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, scale=p.scale,
+                     unit_bytes=args.unit_bytes, dot_task_elems=args.dot_task_elems)
         H64 = None
     else:
         H64 = HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, scale=p.scale,
@@ -380,6 +389,10 @@ def main() -> int:
     tuned = {}
 
     def tune(H, name):
+        if name == "adaptive" and fixed_sizes:
+            tuned[name] = {"unit_bytes": args.unit_bytes, "dot_task_elems": args.dot_task_elems,
+                           "ms": None}
+            return
         if args.no_autotune:
             return
         r = H.autotune()

@@ -96,9 +96,9 @@ __device__ inline Raw4<FMT> load4(const void* base, int64_t i) {
     Raw4<FMT> r;
     const void* p = elem_ptr<FMT>(base, i);
     if constexpr (FMT == HH_FMT_FP64) {
-        r.a = NT ? ldg_nt<dbl2_t>(p) : ldg<dbl2_t>(p);
-        r.b = NT ? ldg_nt<dbl2_t>(static_cast<const dbl2_t*>(p) + 1)
-                 : ldg<dbl2_t>(static_cast<const dbl2_t*>(p) + 1);
+        // two loads share each cache line: no streaming hint (see bload4)
+        r.a = ldg<dbl2_t>(p);
+        r.b = ldg<dbl2_t>(static_cast<const dbl2_t*>(p) + 1);
     } else if constexpr (FMT == HH_FMT_FP32) {
         r.a = NT ? ldg_nt<flt4_t>(p) : ldg<flt4_t>(p);
     } else if constexpr (FMT == HH_FMT_FP16) {
@@ -122,9 +122,10 @@ __device__ inline rsrc_t make_rsrc(const void* base, int64_t bytes) {
 
 // Cache policy of a buffer load: CP_STREAM marks it non-temporal (the
 // single-vector kernels read every factor byte once per product; measured at
-// the benchmark size, the product is 6% faster with it). The several-RHS
-// kernels keep the default policy: their right-hand-side groups re-read a
-// tile's columns from L2.
+// the benchmark size, the product is 6% faster with it). fp64 factors are
+// loaded as two 16-byte halves per lane and keep the default policy, and so do
+// the several-RHS kernels, whose right-hand-side groups re-read a tile's
+// columns from L2.
 constexpr int CP_STREAM = 2;
 
 // Elements at byte offset off .. off + 4 elements of a buffer.
@@ -132,8 +133,10 @@ template <int FMT, int CP = 0>
 __device__ inline Raw4<FMT> bload4(rsrc_t rs, uint32_t off) {
     Raw4<FMT> r;
     if constexpr (FMT == HH_FMT_FP64) {
-        r.a = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, CP));
-        r.b = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, CP));
+        // two loads share each cache line: no streaming hint, or the line can
+        // leave the cache between them
+        r.a = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        r.b = __builtin_bit_cast(dbl2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
     } else if constexpr (FMT == HH_FMT_FP32) {
         r.a = __builtin_bit_cast(flt4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, CP));
     } else if constexpr (FMT == HH_FMT_FP16) {
