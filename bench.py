@@ -262,11 +262,12 @@ def batched_bench(count: int, steps: int, warmup: int) -> int:
     t0 = time.perf_counter()
     hs = []
     for i, p in enumerate(probs):
+        t1 = time.perf_counter()
         hs.append(HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, h=p.h,
                           io_dtype="f32"))
-        if (i + 1) % 32 == 0 or i + 1 == len(probs):
-            print(f"bench: built {i + 1} / {len(probs)} instances, {time.perf_counter() - t0:.1f} s",
-                  file=sys.stderr, flush=True)
+        print(f"bench: instance {i}: N={p.n} tol={p.tol:.0e} h={p.h:.3f} built in "
+              f"{time.perf_counter() - t1:.2f} s ({time.perf_counter() - t0:.1f} s in all)",
+              file=sys.stderr, flush=True)
     t_build = time.perf_counter() - t0
     rng = np.random.default_rng(4)
     xs = [torch.from_numpy(rng.standard_normal(h.n)).float().cuda() for h in hs]

@@ -1118,8 +1118,9 @@ static void ensure_part(hh_handle* h) {
 
 // Frees the device copies of a direction's task tables (before a rebuild).
 static void drop_tasks(hh_handle* h, TaskSet& S) {
-    for (void* p : {(void*)S.d_dot, (void*)S.d_dotm, (void*)S.d_leaf, (void*)S.d_runs,
-                    (void*)S.d_cl_run, (void*)S.d_unit, (void*)S.d_uruns, (void*)S.d_fin})
+    for (void* p : {(void*)S.d_dot, (void*)S.d_dotm, (void*)S.d_dotp, (void*)S.d_pcols,
+                    (void*)S.d_leaf, (void*)S.d_runs, (void*)S.d_cl_run, (void*)S.d_unit,
+                    (void*)S.d_uruns, (void*)S.d_fin})
         if (p) h->mem.release(p);
     S = TaskSet{};
 }
@@ -1390,17 +1391,76 @@ static void build_tasks(hh_handle* h) {
             if (!any) break;
         }
     }
+    // panel tiles: the factors that phase V reads (V for H, U for H^T) in
+    // memory order; blocks stored one after another with the same format,
+    // entry width, stride and x slice form a panel, cut into tiles of
+    // 16 DOTP_MT columns that may span blocks
+    for (int dir = 0; dir < 2; ++dir) {
+        TaskSet& S = dir == 0 ? F : T;
+        std::vector<int64_t> lr;
+        for (size_t i = 0; i < h->blocks.size(); ++i)
+            if (h->blocks[i].lowrank && h->blocks[i].rank > 0) lr.push_back((int64_t)i);
+        auto fptr = [&](int64_t i) {
+            const BlockRec& r = h->blocks[i];
+            return static_cast<const char*>(dir == 0 ? r.v_ptr : r.u_ptr);
+        };
+        std::sort(lr.begin(), lr.end(), [&](int64_t a, int64_t b) { return fptr(a) < fptr(b); });
+        size_t g0 = 0;
+        while (g0 < lr.size()) {
+            const BlockRec& r0 = h->blocks[lr[g0]];
+            const int64_t Pl = dir == 0 ? r0.PJ : r0.PI, xo = dir == 0 ? r0.pJ : r0.pI;
+            const int64_t cbytes = col_bytes(r0.fmt, r0.t, Pl);
+            // the panel: following blocks that continue it in memory
+            size_t g1 = g0 + 1;
+            const char* next = fptr(lr[g0]) + r0.rank * cbytes;
+            while (g1 < lr.size()) {
+                const BlockRec& r = h->blocks[lr[g1]];
+                const int64_t P2 = dir == 0 ? r.PJ : r.PI, x2 = dir == 0 ? r.pJ : r.pI;
+                if (r.fmt != r0.fmt || r.t != r0.t || P2 != Pl || x2 != xo || fptr(lr[g1]) != next) break;
+                next += r.rank * cbytes;
+                ++g1;
+            }
+            const int64_t m0 = (int64_t)S.pcols.size();
+            for (size_t g = g0; g < g1; ++g) {
+                const BlockRec& r = h->blocks[lr[g]];
+                const int64_t base = dir == 0 ? r.col : r.col_t;
+                const int64_t ex = r.eU + r.eV + 1024;
+                for (int64_t j = 0; j < r.rank; ++j) S.pcols.push_back((base + j) | (ex << 40));
+            }
+            const int64_t ncols = (int64_t)S.pcols.size() - m0;
+            for (int64_t c0 = 0; c0 < ncols; c0 += 16 * DOTP_MT) {
+                DotTask t{};
+                t.col0 = fptr(lr[g0]) + c0 * cbytes;
+                t.xoff = xo;
+                t.toff = m0 + c0;                    // map position until the upload
+                t.P = (int32_t)Pl;
+                t.ncols = (int32_t)std::min<int64_t>(16 * DOTP_MT, ncols - c0);
+                t.fmt = r0.fmt;
+                t.hid = 0;
+                t.exp = 0;
+                t.w = r0.fmt == HH_FMT_CONT ? 9 + r0.t : 0;
+                S.dotp.push_back(t);
+            }
+            g0 = g1;
+        }
+    }
     // several-RHS tiles ordered by the cluster of x they read (column cluster
     // for H, row cluster for H^T), so that x_J stays in L2 across its blocks
     for (int dir = 0; dir < 2; ++dir) {
-        std::vector<DotTask>& v = (dir == 0 ? F : T).dotm;
-        std::stable_sort(v.begin(), v.end(), [](const DotTask& a, const DotTask& b) {
-            return std::make_tuple(a.P, a.xoff) < std::make_tuple(b.P, b.xoff);
-        });
+        for (std::vector<DotTask>* v : {&(dir == 0 ? F : T).dotm, &(dir == 0 ? F : T).dotp})
+            std::stable_sort(v->begin(), v->end(), [](const DotTask& a, const DotTask& b) {
+                return std::make_tuple(a.P, a.xoff) < std::make_tuple(b.P, b.xoff);
+            });
     }
     for (TaskSet* S : {&F, &T}) {
+        S->d_pcols = upload(h->mem, S->pcols);
+        for (DotTask& t : S->dotp) {
+            t.cmap = S->d_pcols + t.toff;
+            t.toff = 0;
+        }
         S->d_dot = upload(h->mem, S->dot);
         S->d_dotm = upload(h->mem, S->dotm);
+        S->d_dotp = upload(h->mem, S->dotp);
         S->d_leaf = upload(h->mem, S->leaf);
         S->d_runs = upload(h->mem, S->runs);
         S->d_cl_run = upload(h->mem, S->cl_run);

@@ -88,6 +88,8 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
     if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->has_cont, stream);
+    else if (R <= PANEL_MAX_R && !h->has_cont)
+        launch_dot(d, nullptr, S.d_dotp, (int64_t)S.dotp.size(), R, h->has_cont, stream);
     else launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->has_cont, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[2], (hipStream_t)stream));
     if (R == 1)
@@ -169,7 +171,10 @@ static void product_noalloc(const hh_handle* h, const void* x, void* y, int64_t 
         launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(),
                      h->has_cont, stream);
     } else {
-        launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->has_cont, stream);
+        if (R <= PANEL_MAX_R && !h->has_cont)
+            launch_dot(d, nullptr, S.d_dotp, (int64_t)S.dotp.size(), R, h->has_cont, stream);
+        else
+            launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->has_cont, stream);
         launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, h->has_cont, stream);
     }
     HIPCHK(hipGetLastError());
@@ -239,7 +244,9 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
         for (int t = 0; t < count; ++t) {
             const hh_handle* h = hs[t];
             np->max_np = std::max(np->max_np, h->np);
-            for (DotTask k : (nrhs == 1 ? h->fwd.dot : h->fwd.dotm)) {
+            for (DotTask k : (nrhs == 1 ? h->fwd.dot
+                              : nrhs <= PANEL_MAX_R && !hs[0]->has_cont ? h->fwd.dotp
+                                                                         : h->fwd.dotm)) {
                 k.hid = t;
                 dot.push_back(k);
             }

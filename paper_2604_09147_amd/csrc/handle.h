@@ -22,6 +22,8 @@ struct DevMem {
 struct TaskSet {                      // one direction of the product
     std::vector<DotTask> dot;
     std::vector<DotTask> dotm;        // tiles of at most 16 columns (several RHS)
+    std::vector<DotTask> dotp;        // panel tiles (2 .. PANEL_MAX_R right-hand sides)
+    std::vector<int64_t> pcols;       // their column maps (DotTask::cmap)
     std::vector<LeafTask> leaf;
     std::vector<UnitTask> unit;       // single-vector work units, leaf by leaf
     std::vector<Run> uruns;           // their runs, format-grouped per unit
@@ -30,6 +32,8 @@ struct TaskSet {                      // one direction of the product
     std::vector<int32_t> cl_run;      // NFMT (sum_l 2^(d l)) + 1 boundaries (cluster, format)
     DotTask* d_dot = nullptr;
     DotTask* d_dotm = nullptr;
+    DotTask* d_dotp = nullptr;
+    int64_t* d_pcols = nullptr;
     LeafTask* d_leaf = nullptr;
     UnitTask* d_unit = nullptr;
     Run* d_uruns = nullptr;

@@ -90,6 +90,10 @@ struct DotTask {
     int32_t hid;             // handle index in a batched launch
     int32_t exp;             // eU + eV (power-of-two factor scales, exact)
     int32_t w;               // continuum: bits per stored entry (9 + t); else 0
+    // Panel tiles (columns of several blocks stored one after another): per
+    // column c, cmap[c] = coefficient index | (exponent + 1024) << 40, used
+    // instead of toff + c and exp; null for the columns of one block.
+    const int64_t* cmap;
 };
 
 // Columns stored with a common stride and consecutive coefficients, restricted
@@ -162,6 +166,12 @@ struct BlockRec {
 
 // Columns per several-RHS phase-V tile: DOTM_MT MFMA tiles of 16 columns.
 constexpr int DOTM_MT = 1;
+// Up to PANEL_MAX_R right-hand sides, phase V of handles without continuum
+// blocks runs on panel tiles instead: DOTP_MT x 16 consecutive stored columns
+// of blocks that share the column cluster, format and stride (one x_J load
+// serves all of them).
+constexpr int DOTP_MT = 4;
+constexpr int PANEL_MAX_R = 16;
 
 // Kernel launch wrappers (defined in the .hip files). cont: the handle (or
 // some handle of the batch) stores continuum blocks.

@@ -823,6 +823,20 @@ __device__ inline dbl4_t mfma16(double a, double b, dbl4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Coefficient of tile column cm for right-hand side rhs: at toff + cm with the
+// tile's exponent, or (panel tiles) where the column map sends it.
+template <bool PANEL>
+__device__ inline void dotm_store(const DotTask& t, const Desc& D, int R, int cm, int rhs, double v) {
+    int64_t idx = t.toff + cm;
+    int e = t.exp;
+    if (PANEL) {
+        const int64_t m = ldg<int64_t>(t.cmap + cm);
+        idx = m & (((int64_t)1 << 40) - 1);
+        e = (int)(m >> 40) - 1024;
+    }
+    stg<double>(D.tb + idx * (int64_t)R + rhs, ldexp(v, e));
+}
+
 // Phase V: T[c][r] = 2^e sum_p V[p][c] x[p][r] for a tile of up to 16 MT
 // columns of one block (MT column tiles of 16 share every x load) and NT tiles
 // of 16 right-hand sides (group g). K step = 16 rows: lane (i, k) loads rows
@@ -857,7 +871,7 @@ __device__ void dotm_tile(const DotTask& t, const Desc& D, int R, int g, int lan
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int u = 0; u < NT; ++u) acc[h][mt][u] = dbl4_t{0.0, 0.0, 0.0, 0.0};
-    constexpr int KU = NT * MT == 1 ? 4 : NT * MT == 2 ? 2 : 1;
+    constexpr int KU = NT * MT == 1 ? 4 : (NT * MT == 2 || MT == 4) ? 2 : 1;
     for (int p0 = 0; p0 < P; p0 += 16 * KU) {
         double a[KU][MT][4];
         double b[KU][4][NT];
@@ -897,8 +911,7 @@ __device__ void dotm_tile(const DotTask& t, const Desc& D, int R, int g, int lan
 #pragma unroll
                 for (int h = 1; h < AC; ++h) v += acc[h][mt][u][r];
                 const int cm = 16 * mt + 4 * r + kq, rhs = 16 * (g * NT + u) + i;
-                if (cm < t.ncols && rhs < R)
-                    stg<double>(D.tb + (t.toff + cm) * (int64_t)R + rhs, ldexp(v, t.exp));
+                if (cm < t.ncols && rhs < R) dotm_store<MT == DOTP_MT>(t, D, R, cm, rhs, v);
             }
 }
 
@@ -963,23 +976,22 @@ __device__ void dotm_tile_cont(const DotTask& t, const Desc& D, int R, int g, in
 #pragma unroll
                 for (int h = 1; h < AC; ++h) v += acc[h][mt][u][r];
                 const int cm = 16 * mt + 4 * r + kq, rhs = 16 * (g * NT + u) + i;
-                if (cm < t.ncols && rhs < R)
-                    stg<double>(D.tb + (t.toff + cm) * (int64_t)R + rhs, ldexp(v, t.exp));
+                if (cm < t.ncols && rhs < R) dotm_store<MT == DOTP_MT>(t, D, R, cm, rhs, v);
             }
 }
 
-template <int NT>
+template <int NT, int MT>
 struct DotmCont {
     DotTask t;
     Desc D;
     int R, g, lane;
     template <int W>
-    __device__ void operator()() const { dotm_tile_cont<W, NT, DOTM_MT>(t, D, R, g, lane); }
+    __device__ void operator()() const { dotm_tile_cont<W, NT, MT>(t, D, R, g, lane); }
 };
 
 // Tiles x right-hand-side groups, four per workgroup (one per wave); the groups
 // of one tile are neighbours, so its columns are read from HBM about once.
-template <int NT, bool CONT>
+template <int NT, bool CONT, int MT>
 __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, const DotTask* tiles,
                                                    int64_t ntiles, int R, int ngroups) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -990,14 +1002,14 @@ __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, co
     const DotTask t = ldrec<DotTask>(tiles + ti);
     const Desc D = descs ? ldrec<Desc>(descs + t.hid) : d;
     if (CONT && t.fmt == HH_FMT_CONT) {
-        if constexpr (CONT) with_width(t.w, DotmCont<NT>{t, D, R, g, lane});
+        if constexpr (CONT) with_width(t.w, DotmCont<NT, MT>{t, D, R, g, lane});
         return;
     }
     switch (t.fmt) {
-        case HH_FMT_FP64: dotm_tile<HH_FMT_FP64, NT, DOTM_MT>(t, D, R, g, lane); break;
-        case HH_FMT_FP32: dotm_tile<HH_FMT_FP32, NT, DOTM_MT>(t, D, R, g, lane); break;
-        case HH_FMT_FP16: dotm_tile<HH_FMT_FP16, NT, DOTM_MT>(t, D, R, g, lane); break;
-        default: dotm_tile<HH_FMT_BF16, NT, DOTM_MT>(t, D, R, g, lane); break;
+        case HH_FMT_FP64: dotm_tile<HH_FMT_FP64, NT, MT>(t, D, R, g, lane); break;
+        case HH_FMT_FP32: dotm_tile<HH_FMT_FP32, NT, MT>(t, D, R, g, lane); break;
+        case HH_FMT_FP16: dotm_tile<HH_FMT_FP16, NT, MT>(t, D, R, g, lane); break;
+        default: dotm_tile<HH_FMT_BF16, NT, MT>(t, D, R, g, lane); break;
     }
 }
 
@@ -1178,15 +1190,18 @@ static void launch_dotm(const Desc& d, const Desc* descs, const DotTask* tasks, 
     const int nt = rhs_tiles_per_group(R);
     const int ngroups = ((R + 15) / 16 + nt - 1) / nt;
     const unsigned grid = (unsigned)((ntasks * ngroups + 3) / 4);
-    if (nt == 1)
-        hipLaunchKernelGGL((dotm_kernel<1, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
-                           descs, tasks, ntasks, R, ngroups);
+    if (!CONT && R <= PANEL_MAX_R)
+        hipLaunchKernelGGL((dotm_kernel<1, false, DOTP_MT>), dim3(grid), dim3(256), 0,
+                           (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
+    else if (nt == 1)
+        hipLaunchKernelGGL((dotm_kernel<1, CONT, DOTM_MT>), dim3(grid), dim3(256), 0,
+                           (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
     else if (nt == 2)
-        hipLaunchKernelGGL((dotm_kernel<2, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
-                           descs, tasks, ntasks, R, ngroups);
+        hipLaunchKernelGGL((dotm_kernel<2, CONT, DOTM_MT>), dim3(grid), dim3(256), 0,
+                           (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
     else
-        hipLaunchKernelGGL((dotm_kernel<4, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
-                           descs, tasks, ntasks, R, ngroups);
+        hipLaunchKernelGGL((dotm_kernel<4, CONT, DOTM_MT>), dim3(grid), dim3(256), 0,
+                           (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
 }
 
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks, int R,
@@ -1201,7 +1216,8 @@ void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t 
                                d, descs, tasks);
         return;
     }
-    // several right-hand sides: tasks are tiles of at most 16 columns
+    // several right-hand sides: panel tiles (up to PANEL_MAX_R right-hand
+    // sides, fixed formats only), else tiles of at most 16 columns
     if (cont) launch_dotm<true>(d, descs, tasks, ntasks, R, stream);
     else launch_dotm<false>(d, descs, tasks, ntasks, R, stream);
 }
