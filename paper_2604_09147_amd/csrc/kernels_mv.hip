@@ -177,6 +177,7 @@ __device__ inline double wave_sum(double v) {
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+
 // ------------------------------------------------------ continuum storage
 // A continuum column holds its entries back to back, W = 9 + t bits each, in
 // little-endian bit order (entry i at bits [i W, i W + W) of the column); an
@@ -848,11 +849,15 @@ __device__ void dotm_tile(const DotTask& t, const Desc& D, int R, int g, int lan
     constexpr uint32_t es = elem_bytes<FMT>();
     const int i = lane & 15, kq = lane >> 4;
     const int P = t.P;
-    rsrc_t rs[MT];
+    // one wave-uniform descriptor for the tile; the column goes into the
+    // lane's offset (a per-lane descriptor would make every load a loop over
+    // the distinct descriptors of the wave)
+    const rsrc_t rs = make_rsrc(t.col0, (int64_t)t.ncols * P * es);
+    uint32_t cofs[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int c = 16 * mt + i < t.ncols ? 16 * mt + i : t.ncols - 1;
-        rs[mt] = make_rsrc(static_cast<const char*>(t.col0) + (int64_t)c * P * es, (int64_t)P * es);
+        cofs[mt] = (uint32_t)c * (uint32_t)P * es;
     }
     const double* xb = D.xt + t.xoff * (int64_t)R;
     int rr[NT];
@@ -882,7 +887,7 @@ __device__ void dotm_tile(const DotTask& t, const Desc& D, int R, int g, int lan
             pok[s] = p < P;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                widen4<FMT, double>(bload4<FMT>(rs[mt], (uint32_t)(pok[s] ? p : 0) * es), a[s][mt]);
+                widen4<FMT, double>(bload4<FMT>(rs, cofs[mt] + (uint32_t)(pok[s] ? p : 0) * es), a[s][mt]);
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -922,11 +927,12 @@ __device__ void dotm_tile_cont(const DotTask& t, const Desc& D, int R, int g, in
     const int i = lane & 15, kq = lane >> 4;
     const int P = t.P;
     const int64_t cb = cont_col_bytes(P, W);
-    rsrc_t rs[MT];
+    const rsrc_t rs = make_rsrc(t.col0, (int64_t)t.ncols * cb);   // wave-uniform (see dotm_tile)
+    uint32_t cofs[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int c = 16 * mt + i < t.ncols ? 16 * mt + i : t.ncols - 1;
-        rs[mt] = make_rsrc(static_cast<const char*>(t.col0) + (int64_t)c * cb, cb);
+        cofs[mt] = (uint32_t)c * (uint32_t)cb;
     }
     const double* xb = D.xt + t.xoff * (int64_t)R;
     int rr[NT];
@@ -950,7 +956,7 @@ __device__ void dotm_tile_cont(const DotTask& t, const Desc& D, int R, int g, in
         cpos<W>(pok ? p : 0, off, sh);
         double a[MT][4];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) cwiden<W>(cload<W>(rs[mt], off), sh, a[mt]);
+        for (int mt = 0; mt < MT; ++mt) cwiden<W>(cload<W>(rs, cofs[mt] + off), sh, a[mt]);
         double b[4][NT];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
