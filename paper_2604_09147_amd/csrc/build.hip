@@ -1391,6 +1391,26 @@ static void build_tasks(hh_handle* h) {
             if (!any) break;
         }
     }
+    // several-RHS accumulation: one workgroup per leaf, so leaves go heaviest
+    // first (their factor bytes), which shortens the tail of the launch; the
+    // single-vector work units keep their own order
+    for (TaskSet* S : {&F, &T}) {
+        std::vector<std::pair<double, LeafTask>> wl;
+        for (const LeafTask& lt : S->leaf) {
+            double w = 0.0;
+            for (int l = 0; l <= L; ++l) {
+                const int64_t ci = first[l] + ((int64_t)lt.leaf >> (d * (L - l)));
+                for (int32_t k = S->cl_run[NFMT * ci]; k < S->cl_run[NFMT * ci + NFMT]; ++k) {
+                    const Run& rn = S->runs[k];
+                    w += (double)rn.ncols * (rn.fmt == HH_FMT_CONT ? rn.w / 8.0 : fmt_size(rn.fmt));
+                }
+            }
+            wl.push_back({w * lt.P, lt});
+        }
+        std::stable_sort(wl.begin(), wl.end(),
+                         [](const auto& a, const auto& b) { return a.first > b.first; });
+        for (size_t k = 0; k < wl.size(); ++k) S->leaf[k] = wl[k].second;
+    }
     // panel tiles: the factors that phase V reads (V for H, U for H^T) in
     // memory order; blocks stored one after another with the same format,
     // entry width, stride and x slice form a panel, cut into tiles of
