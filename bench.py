@@ -245,6 +245,102 @@ def switch_level_bench(n: int) -> int:
     return 0
 
 
+def workload_bench(name: str, steps: int, warmup: int) -> int:
+    """The other two configurations of the benchmark set, timed with graph
+    replays like the headline: the 2D 1/r matrix (adaptive vs uniform fp64, 1
+    and 64 right-hand sides) and the double-layer matrix (16 fp32 right-hand
+    sides, the product with H and with H^T, as an autograd forward and
+    backward pass would run them)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2604_09147_amd import HMatrix
+
+    torch.cuda.set_device(0)
+    torch.zeros(1, device="cuda")
+    res = {}
+    if name == "2d":
+        p = W.cfg_2d_inv_r()
+        t0 = time.perf_counter()
+        H64 = HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size, scale=p.scale,
+                      uniform_fp64=True)
+        Ha = H64.derive(mask=0xF)
+        t_build = time.perf_counter() - t0
+        for H, tag in ((Ha, "adaptive"), (H64, "uniform_fp64")):
+            H.autotune()
+            st = H.stats()
+            for R in (1, 64):
+                shape = (p.n,) if R == 1 else (p.n, R)
+                x = torch.from_numpy(W.rhs(p.n, R, np.random.default_rng(R))).reshape(shape).cuda()
+                y = torch.empty_like(x)
+                wall, med = graph_timing(H, x, y, steps, warmup)
+                res[f"{tag}_nrhs{R}"] = {"ms_per_step": 1e3 * wall / steps,
+                                         "graph_replay_ms_median": round(med, 4),
+                                         "rhs_products_per_s": R * steps / wall,
+                                         "hbm_gbs": st["matvec_bytes"] / (wall / steps) / 1e9}
+                print(f"bench: {tag}, {R} RHS: {1e3 * wall / steps:.3f} ms", file=sys.stderr, flush=True)
+        res["speedup_vs_uniform_fp64_nrhs1"] = (res["uniform_fp64_nrhs1"]["ms_per_step"] /
+                                                res["adaptive_nrhs1"]["ms_per_step"])
+        value, unit = res["adaptive_nrhs1"]["rhs_products_per_s"], "matvec/s"
+        ms = res["adaptive_nrhs1"]["ms_per_step"]
+        dtype = "f64"
+        cfg = {"workload": f"2D 1/r, N={p.n} uniform in [0,1]^2, leaf {p.leaf_size}, eta {p.eta}, "
+                           f"switch level {p.switch_level}, tol {p.tol}, adaptive fp64/fp32/fp16/bf16, "
+                           "nrhs 1 (and 64)", "n": p.n, "nrhs": 1, "build_seconds": round(t_build, 2),
+               "timing": "graph replays", "parallelism": "1 GPU"}
+        blocks = Ha.stats()["blocks_by_format"]
+        H64.free()
+        Ha.free()
+    else:
+        p = W.cfg_double_layer()
+        t0 = time.perf_counter()
+        H = HMatrix(p.points, p.kernel, p.tol, p.eta, p.switch_level, p.leaf_size,
+                    normals=p.normals, io_dtype="f32")
+        t_build = time.perf_counter() - t0
+        H.autotune()
+        st = H.stats()
+        x = torch.from_numpy(W.rhs(p.n, 16, np.random.default_rng(5), np.float32)).cuda()
+        for trans in (False, True):
+            y = torch.empty_like(x)
+            H.reserve(16)
+            (H.matvec_t if trans else H.matvec)(x, out=y)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                (H.matvec_t if trans else H.matvec)(x, out=y)
+            for _ in range(warmup):
+                graph.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                graph.replay()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            tag = "transpose" if trans else "forward"
+            res[tag] = {"ms_per_step": 1e3 * wall / steps, "rhs_products_per_s": 16 * steps / wall,
+                        "hbm_gbs": st["matvec_bytes"] / (wall / steps) / 1e9}
+            print(f"bench: double layer {tag}, 16 RHS: {1e3 * wall / steps:.3f} ms", file=sys.stderr,
+                  flush=True)
+            del graph
+        value, unit = res["forward"]["rhs_products_per_s"], "RHS-products/s"
+        ms = res["forward"]["ms_per_step"] + res["transpose"]["ms_per_step"]
+        dtype = "f32 io, f64 accumulation"
+        cfg = {"workload": f"double layer n_j.(p_i-p_j)/|p_i-p_j|^3, N={p.n} (half on the unit "
+                           "sphere, half in the ball), leaf 256, eta 1.5, switch level 3, tol 1e-6, "
+                           "16 fp32 RHS, H x then H^T g", "n": p.n, "nrhs": 16,
+               "build_seconds": round(t_build, 2), "timing": "graph replays", "parallelism": "1 GPU"}
+        blocks = st["blocks_by_format"]
+        H.free()
+    out = {"metric": f"H_h products, {name} workload", "value": round(value, 3), "unit": unit,
+           "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded points, x ~ N(0,1))", "config": cfg,
+           "blocks_by_format": [int(v) for v in blocks], "results": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def batched_bench(count: int, steps: int, warmup: int) -> int:
     """Independent Gaussian-kernel instances (N log-uniform in [2^10, 2^16], tol
     from {1e-4, 1e-6, 1e-8}, h ~ U[0.05, 0.3]), each built on the GPU with its
@@ -333,6 +429,9 @@ def main() -> int:
     ap.add_argument("--batched", type=int, default=0, metavar="K",
                     help="time the batched workload instead: the first K of the 512 Gaussian "
                          "instances, one fp32 RHS each, in one launch per phase")
+    ap.add_argument("--workload", default="headline", choices=["headline", "2d", "double_layer"],
+                    help="2d: the 2D 1/r matrix (N=2^18, nrhs 1 and 64, adaptive vs uniform fp64); "
+                         "double_layer: the double-layer matrix (N=2^19, 16 fp32 RHS, H and H^T)")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -346,6 +445,8 @@ def main() -> int:
         return switch_level_bench(args.n)
     if args.batched:
         return batched_bench(args.batched, args.steps, args.warmup)
+    if args.workload != "headline":
+        return workload_bench(args.workload, args.steps, args.warmup)
     multi = [int(v) for v in args.multi_rhs.split(",") if v.strip()]
 
     # CPU baseline in a child process, overlapped with the GPU build
