@@ -250,7 +250,9 @@ def workload_bench(name: str, steps: int, warmup: int) -> int:
     replays like the headline: the 2D 1/r matrix (adaptive vs uniform fp64, 1
     and 64 right-hand sides) and the double-layer matrix (16 fp32 right-hand
     sides, the product with H and with H^T, as an autograd forward and
-    backward pass would run them)."""
+    backward pass would run them). q43: the 3D Laplace points at tol 1e-2,
+    where the format rule picks the 8-bit q43 format for most blocks, with
+    and without it in the mask (1 and 16 right-hand sides)."""
     import numpy as np
     import torch
 
@@ -292,6 +294,45 @@ def workload_bench(name: str, steps: int, warmup: int) -> int:
         blocks = Ha.stats()["blocks_by_format"]
         H64.free()
         Ha.free()
+    elif name == "q43":
+        p = W.cfg_3d_laplace()
+        tol = 1e-2
+        t0 = time.perf_counter()
+        H64 = HMatrix(p.points, p.kernel, tol, p.eta, p.switch_level, p.leaf_size, scale=p.scale,
+                      uniform_fp64=True)
+        Hq = H64.derive(mask=0x2F)
+        t_build = time.perf_counter() - t0
+        Hf = H64.derive(mask=0xF)
+        H64.free()
+        for H, tag in ((Hq, "with_q43"), (Hf, "without_q43")):
+            H.autotune()
+            st = H.stats()
+            for R in (1, 16):
+                shape = (p.n,) if R == 1 else (p.n, R)
+                x = torch.from_numpy(W.rhs(p.n, R, np.random.default_rng(R))).reshape(shape).cuda()
+                y = torch.empty_like(x)
+                wall, med = graph_timing(H, x, y, steps, warmup)
+                res[f"{tag}_nrhs{R}"] = {"ms_per_step": 1e3 * wall / steps,
+                                         "graph_replay_ms_median": round(med, 4),
+                                         "rhs_products_per_s": R * steps / wall,
+                                         "matvec_bytes": st["matvec_bytes"],
+                                         "hbm_gbs": st["matvec_bytes"] / (wall / steps) / 1e9,
+                                         "blocks_by_format": [int(v) for v in st["blocks_by_format"]]}
+                print(f"bench: {tag}, {R} RHS: {1e3 * wall / steps:.3f} ms", file=sys.stderr, flush=True)
+            x = torch.from_numpy(W.rhs(p.n, 1, np.random.default_rng(9))).cuda()
+            res[f"{tag}_y"] = H.matvec(x)
+        d = res.pop("with_q43_y") - res["without_q43_y"]
+        res["rel_diff_with_vs_without_q43"] = float(d.norm() / res.pop("without_q43_y").norm())
+        value, unit = res["with_q43_nrhs1"]["rhs_products_per_s"], "matvec/s"
+        ms = res["with_q43_nrhs1"]["ms_per_step"]
+        dtype = "q43/bf16 storage, fp32 + f64 arithmetic"
+        cfg = {"workload": f"3D Laplace, N={p.n} uniform in [0,1]^3, leaf {p.leaf_size}, eta {p.eta}, "
+                           f"switch level {p.switch_level}, tol {tol}, mask fp64/fp32/fp16/bf16/q43 "
+                           "(and without q43), nrhs 1 (and 16)", "n": p.n, "nrhs": 1,
+               "build_seconds": round(t_build, 2), "timing": "graph replays", "parallelism": "1 GPU"}
+        blocks = Hq.stats()["blocks_by_format"]
+        Hq.free()
+        Hf.free()
     else:
         p = W.cfg_double_layer()
         t0 = time.perf_counter()
@@ -429,9 +470,10 @@ def main() -> int:
     ap.add_argument("--batched", type=int, default=0, metavar="K",
                     help="time the batched workload instead: the first K of the 512 Gaussian "
                          "instances, one fp32 RHS each, in one launch per phase")
-    ap.add_argument("--workload", default="headline", choices=["headline", "2d", "double_layer"],
+    ap.add_argument("--workload", default="headline", choices=["headline", "2d", "double_layer", "q43"],
                     help="2d: the 2D 1/r matrix (N=2^18, nrhs 1 and 64, adaptive vs uniform fp64); "
-                         "double_layer: the double-layer matrix (N=2^19, 16 fp32 RHS, H and H^T)")
+                         "double_layer: the double-layer matrix (N=2^19, 16 fp32 RHS, H and H^T); "
+                         "q43: the 3D Laplace points at tol 1e-2 with and without q43 storage")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:

@@ -63,8 +63,11 @@ typedef enum {
  * the continuum format of the accessor remark of Sec. 4.3: per block t
  * fraction bits (7 <= t <= 23) behind a sign and an 8-bit exponent with fp32's
  * range and gradual underflow, 9 + t bits per entry, round to nearest even
- * (t = 7 is bf16, t = 23 fp32). */
-enum { HH_FMT_FP64 = 0, HH_FMT_FP32 = 1, HH_FMT_FP16 = 2, HH_FMT_BF16 = 3, HH_FMT_CONT = 4 };
+ * (t = 7 is bf16, t = 23 fp32). HH_FMT_Q43 is the 8-bit row of the table: a
+ * sign, 4 exponent bits (bias 7) and 3 fraction bits, gradual underflow below
+ * 2^-6, largest value 240, one byte per entry. */
+enum { HH_FMT_FP64 = 0, HH_FMT_FP32 = 1, HH_FMT_FP16 = 2, HH_FMT_BF16 = 3, HH_FMT_CONT = 4,
+       HH_FMT_Q43 = 5 };
 /* Element type of x and y in the products. */
 enum { HH_IO_F64 = 0, HH_IO_F32 = 1 };
 
@@ -85,14 +88,16 @@ typedef struct {
 } hh_kernel;
 
 typedef struct {
-    uint32_t precision_mask; /* bit f set = format f available to the rule;
-                                fp64 is always available. 0 means 0xF            */
+    uint32_t precision_mask; /* bit f set = format f available to the rule
+                                (bits 0-3: fp64, fp32, fp16, bf16; bit 5: q43,
+                                the 8-bit row of Table tab:precisions, tried
+                                first); fp64 is always available. 0 means 0xF */
     int uniform_fp64;        /* 1: store every factor in fp64 (same tree, partition
                                 and ranks); the uniform-precision baseline        */
     int io_dtype;            /* HH_IO_F64 (default) or HH_IO_F32 for x and y       */
     uint64_t seed;           /* key of the randomized-compression sketches          */
     int continuum;           /* 1: continuum storage (HH_FMT_CONT) instead of the
-                                mask's formats: each block takes the fewest
+                                mask's formats (q43 included): each block takes the fewest
                                 fraction bits t in [7, 23] whose unit roundoff
                                 2^-(t+1) passes the rule, else fp64. 2: the same
                                 with t in {7, 15, 23} only (16-, 24- and 32-bit
@@ -109,8 +114,8 @@ typedef struct {
     int64_t n_blocks_lowrank;             /* low-rank blocks with rank > 0             */
     int64_t n_blocks_rank0;               /* admissible blocks compressed to rank 0    */
     int64_t n_blocks_dense;               /* dense blocks (diagonal + dense neighbours) */
-    int64_t blocks_by_format[5];          /* low-rank blocks per HH_FMT_*              */
-    int64_t factor_bytes_by_format[5];    /* device bytes of U and V per format        */
+    int64_t blocks_by_format[6];          /* low-rank blocks per HH_FMT_*              */
+    int64_t factor_bytes_by_format[6];    /* device bytes of U and V per format        */
     int64_t dense_bytes;                  /* device bytes of dense blocks (fp64)       */
     int64_t lowrank_entries;              /* sum_b k_b (m_b + n_b)                     */
     int64_t dense_entries;                /* sum m n over dense blocks                 */
@@ -231,7 +236,8 @@ hh_status hh_matvec_timed(const hh_handle* h, const void* x, void* y, int64_t nr
 /* hh_matvec_batch: y_t = H_t^ x_t (Alg. 4) for `count` independent handles in
  * one pass of the kernels (one launch per phase over all handles). Every
  * handle must share io_dtype and the device, and either all or none of them
- * may hold continuum storage (HH_ENOTSUP otherwise); x[t], y[t] are DEVICE pointers
+ * may hold continuum storage (HH_ENOTSUP otherwise; handles with and without
+ * q43 blocks mix freely); x[t], y[t] are DEVICE pointers
  * sized for handle t (N_t x nrhs, row-major). The task tables of the last
  * batch (same handles in the same order, same nrhs) stay on the device, so a
  * repeated call only uploads the x / y descriptors on `stream` and returns
@@ -349,9 +355,11 @@ void hh_plan_free(hh_plan* p);
 
 /* hh_quantize: the library's storage rounding on the host: out[i] = round(in[i]
  * 2^-e) 2^e with round-to-nearest-even straight from float64 to `format`
- * (HH_FMT_*), gradual underflow kept. This is the arithmetic hh_build applies
- * to every factor (e = 0 for fp64 / fp32; the build picks e per factor so that
- * the largest entry lands in [2^14, 2^15) for fp16 and in [1, 2) for bf16). */
+ * (HH_FMT_*, not HH_FMT_CONT), gradual underflow kept. This is the arithmetic
+ * hh_build applies to every factor (e = 0 for fp64 / fp32; the build picks e
+ * per factor so that the largest entry lands in [2^14, 2^15) for fp16, in
+ * [1, 2) for bf16 and in [64, 128) for q43, whose magnitudes past 240 saturate
+ * to 240). */
 hh_status hh_quantize(const double* in, int64_t n, int format, int e, double* out);
 
 /* hh_quantize_cont: the continuum storage rounding on the host: out[i] = the

@@ -98,9 +98,12 @@ void DevMem::free_all() {
     ptrs.clear();
 }
 
-static size_t fmt_size(int fmt) { return fmt == HH_FMT_FP64 ? 8 : fmt == HH_FMT_FP32 ? 4 : 2; }
-static const double UNIT[4] = {0x1p-53, 0x1p-24, 0x1p-11, 0x1p-8};
-static const int BITS[4] = {64, 32, 16, 16};
+static size_t fmt_size(int fmt) {
+    return fmt == HH_FMT_FP64 ? 8 : fmt == HH_FMT_FP32 ? 4 : fmt == HH_FMT_Q43 ? 1 : 2;
+}
+// unit roundoffs and storage bits by HH_FMT_* (index HH_FMT_CONT unused: per block)
+static const double UNIT[NFMT_CODES] = {0x1p-53, 0x1p-24, 0x1p-11, 0x1p-8, 0.0, 0x1p-4};
+static const int BITS[NFMT_CODES] = {64, 32, 16, 16, 0, 8};
 // Storage bits per entry of a block's format (continuum: 9 + t).
 static int entry_bits(int fmt, int t) { return fmt == HH_FMT_CONT ? 9 + t : BITS[fmt]; }
 // Device bytes of one stored column of P (padded) rows.
@@ -926,7 +929,7 @@ struct Builder {
 
     // Alg. 3 storage: round every low-rank factor into its format's arena.
     void pack(bool in_place_ok = true) {
-        int64_t need[NFMT] = {0, 0, 0, 0, 0};            // bytes per format
+        int64_t need[NFMT_CODES] = {0, 0, 0, 0, 0, 0};   // bytes per format
         std::vector<int64_t> lr;
         for (size_t i = 0; i < h->blocks.size(); ++i) {
             const BlockRec& r = h->blocks[i];
@@ -935,9 +938,10 @@ struct Builder {
                 need[r.fmt] += (int64_t)r.rank * (col_bytes(r.fmt, r.t, r.PI) + col_bytes(r.fmt, r.t, r.PJ));
             }
         }
-        bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0 && need[4] == 0;
+        bool all64 = need[1] == 0 && need[2] == 0 && need[3] == 0 && need[4] == 0 && need[5] == 0;
         h->all_fp64 = all64;
         h->has_cont = need[HH_FMT_CONT] > 0;
+        h->family = h->has_cont ? FAM_CONT : need[HH_FMT_Q43] > 0 ? FAM_Q43 : FAM_FIX;
         if (all64 && in_place_ok) {
             // The fp64 store can serve as the arena as it is; it is re-laid in
             // cluster order (longer runs in the product) only if a second copy
@@ -946,7 +950,7 @@ struct Builder {
             HIPCHK(hipMemGetInfo(&fr, &tot));
             if ((double)fr < (double)need[0] + (double)(4ull << 30)) return;
         }
-        // exponents of the scaled formats (fp16, bf16)
+        // exponents of the scaled formats (fp16, bf16, q43)
         std::vector<double> mx(2 * lr.size(), 0.0);
         {
             std::vector<SumItem> items;
@@ -965,13 +969,13 @@ struct Builder {
                 HIPCHK(hipMemcpy(mx.data() + a, out, part.size() * 8, hipMemcpyDeviceToHost));
             }
         }
-        char* arena[NFMT] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-        for (int f = 0; f < NFMT; ++f)
+        char* arena[NFMT_CODES] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        for (int f = 0; f < NFMT_CODES; ++f)
             if (need[f]) arena[f] = static_cast<char*>(h->mem.alloc((size_t)need[f] + 256, false));
         // Arena of a format: every U in (level, row box, column box) order, then
         // every V in (level, column box, row box) order, so that the factors
         // of one cluster and format follow each other (one strided matrix).
-        int64_t offU[NFMT] = {0, 0, 0, 0, 0}, offV[NFMT] = {0, 0, 0, 0, 0};
+        int64_t offU[NFMT_CODES] = {0, 0, 0, 0, 0, 0}, offV[NFMT_CODES] = {0, 0, 0, 0, 0, 0};
         for (int64_t i : lr) {
             const BlockRec& r = h->blocks[i];
             offV[r.fmt] += (int64_t)r.rank * col_bytes(r.fmt, r.t, r.PI);
@@ -984,10 +988,13 @@ struct Builder {
         for (size_t a = 0; a < lr.size(); ++a) {
             BlockRec& r = h->blocks[lr[a]];
             auto expo = [&](double m) {
-                if ((r.fmt != HH_FMT_FP16 && r.fmt != HH_FMT_BF16) || m == 0.0) return 0;
+                if ((r.fmt != HH_FMT_FP16 && r.fmt != HH_FMT_BF16 && r.fmt != HH_FMT_Q43) ||
+                    m == 0.0)
+                    return 0;
                 int q;
                 std::frexp(m, &q);
-                return r.fmt == HH_FMT_FP16 ? q - 1 - 14 : q - 1;
+                // largest entry scaled into [2^14, 2^15) (fp16), [1, 2) (bf16), [64, 128) (q43)
+                return r.fmt == HH_FMT_FP16 ? q - 1 - 14 : r.fmt == HH_FMT_Q43 ? q - 1 - 6 : q - 1;
             };
             r.eU = expo(mx[2 * a]);
             r.eV = expo(mx[2 * a + 1]);
@@ -1177,7 +1184,7 @@ static void build_tasks(hh_handle* h) {
                 t.ncols = (int32_t)std::min<int64_t>(cpt, r.rank - c0);
                 t.fmt = r.fmt;
                 t.hid = 0;
-                t.exp = r.eU + r.eV;
+                t.exp = r.eU + r.eV + fmt_exp_bias(r.fmt);
                 t.w = wbits;
                 (pass == 0 ? F : T).dot.push_back(t);
             }
@@ -1190,7 +1197,7 @@ static void build_tasks(hh_handle* h) {
                 t.ncols = (int32_t)std::min<int64_t>(16 * DOTM_MT, r.rank - c0);
                 t.fmt = r.fmt;
                 t.hid = 0;
-                t.exp = r.eU + r.eV;
+                t.exp = r.eU + r.eV + fmt_exp_bias(r.fmt);
                 t.w = wbits;
                 (pass == 0 ? F : T).dotm.push_back(t);
             }
@@ -1300,13 +1307,14 @@ static void build_tasks(hh_handle* h) {
                 lst.push_back(piece);
             }
         }
-        // within a cluster, runs grouped by format (fp64, fp32, fp16, bf16)
+        // within a cluster, runs grouped by format slot (fp64, fp32, fp16,
+        // bf16, continuum or q43)
         S.cl_run.assign(NFMT * ncl + 1, 0);
         for (int64_t c = 0; c < ncl; ++c)
             for (int f = 0; f < NFMT; ++f) {
                 S.cl_run[NFMT * c + f] = (int32_t)S.runs.size();
                 for (const Run& rn : per[c])
-                    if (rn.fmt == f) S.runs.push_back(rn);
+                    if (fmt_slot(rn.fmt) == f) S.runs.push_back(rn);
             }
         S.cl_run[NFMT * ncl] = (int32_t)S.runs.size();
         for (int64_t lf = 0; lf < nleaf; ++lf) {
@@ -1335,7 +1343,7 @@ static void build_tasks(hh_handle* h) {
                 for (int l = 0; l <= L; ++l) {
                     const int64_t ci = first[l] + ((int64_t)lt.leaf >> (d * (L - l)));
                     for (const Run& rn : per[ci]) {
-                        if (rn.fmt != f) continue;
+                        if (fmt_slot(rn.fmt) != f) continue;
                         const int64_t colb = std::max<int64_t>(
                             1, std::min<int64_t>(UNIT_BYTES / std::max<int64_t>(slice_bytes(rn, lt.P), 1),
                                                  run_lim / run_col_bytes(rn)));
@@ -1366,7 +1374,7 @@ static void build_tasks(hh_handle* h) {
                 ut.rb = (int32_t)S.uruns.size();
                 for (int f = 0; f < NFMT; ++f) {
                     for (size_t i = a; i < e; ++i)
-                        if (list[i].fmt == f) S.uruns.push_back(list[i]);
+                        if (fmt_slot(list[i].fmt) == f) S.uruns.push_back(list[i]);
                     ut.fe[f] = (int32_t)S.uruns.size();
                 }
                 ut.hid = 0;
@@ -1444,7 +1452,7 @@ static void build_tasks(hh_handle* h) {
             for (size_t g = g0; g < g1; ++g) {
                 const BlockRec& r = h->blocks[lr[g]];
                 const int64_t base = dir == 0 ? r.col : r.col_t;
-                const int64_t ex = r.eU + r.eV + 1024;
+                const int64_t ex = r.eU + r.eV + fmt_exp_bias(r.fmt) + 1024;
                 for (int64_t j = 0; j < r.rank; ++j) S.pcols.push_back((base + j) | (ex << 40));
             }
             const int64_t ncols = (int64_t)S.pcols.size() - m0;
@@ -1513,7 +1521,7 @@ static void choose_lowrank_format(const BlockRec& r, double total2, int d, doubl
         fmt = HH_FMT_FP64;
         return;
     }
-    const int order[3] = {HH_FMT_BF16, HH_FMT_FP16, HH_FMT_FP32};
+    const int order[4] = {HH_FMT_Q43, HH_FMT_BF16, HH_FMT_FP16, HH_FMT_FP32};
     for (int f : order) {
         if (!(o.precision_mask & (1u << f))) continue;
         const double u = UNIT[f];
@@ -1606,7 +1614,7 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
     o.precision_mask = 0xF;
     if (opt) o = *opt;
     if (o.precision_mask == 0) o.precision_mask = 0xF;
-    if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
+    if (o.precision_mask & ~0x2Fu) fail(HH_EINVAL, "precision_mask has bits outside 0x2F");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
     if (o.continuum < 0 || o.continuum > 2) fail(HH_EINVAL, "continuum must be 0, 1 or 2");
     if (o.unit_bytes < 0 || o.dot_task_elems < 0) fail(HH_EINVAL, "task sizes must be >= 0");
@@ -1738,7 +1746,7 @@ hh_handle* derive_handle(const hh_handle* src, const hh_options* opt) {
     o.precision_mask = 0xF;
     if (opt) o = *opt;
     if (o.precision_mask == 0) o.precision_mask = 0xF;
-    if (o.precision_mask & ~0xFu) fail(HH_EINVAL, "precision_mask has bits beyond 0xF");
+    if (o.precision_mask & ~0x2Fu) fail(HH_EINVAL, "precision_mask has bits outside 0x2F");
     if (o.io_dtype != HH_IO_F64 && o.io_dtype != HH_IO_F32) fail(HH_EINVAL, "io_dtype must be HH_IO_F64 or HH_IO_F32");
     if (o.continuum < 0 || o.continuum > 2) fail(HH_EINVAL, "continuum must be 0, 1 or 2");
     if (o.unit_bytes < 0 || o.dot_task_elems < 0) fail(HH_EINVAL, "task sizes must be >= 0");

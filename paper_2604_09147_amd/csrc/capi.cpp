@@ -24,7 +24,9 @@ hh_handle* build_handle(const double* points, int64_t n, int d, const hh_kernel*
                         double eta, int switch_level, int leaf_size, const hh_options* opt);
 hh_handle* derive_handle(const hh_handle* src, const hh_options* opt);
 
-static size_t fmt_size(int fmt) { return fmt == HH_FMT_FP64 ? 8 : fmt == HH_FMT_FP32 ? 4 : 2; }
+static size_t fmt_size(int fmt) {
+    return fmt == HH_FMT_FP64 ? 8 : fmt == HH_FMT_FP32 ? 4 : fmt == HH_FMT_Q43 ? 1 : 2;
+}
 
 #define HIPCHK(x)                                                                          \
     do {                                                                                   \
@@ -87,16 +89,16 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     }
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
-    if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->has_cont, stream);
+    if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->family, stream);
     else if (R <= PANEL_MAX_R && !h->has_cont)
-        launch_dot(d, nullptr, S.d_dotp, (int64_t)S.dotp.size(), R, h->has_cont, stream);
-    else launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->has_cont, stream);
+        launch_dot(d, nullptr, S.d_dotp, (int64_t)S.dotp.size(), R, h->family, stream);
+    else launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->family, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[2], (hipStream_t)stream));
     if (R == 1)
         launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(),
-                     h->has_cont, stream);
+                     h->family, stream);
     else
-        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, h->has_cont, stream);
+        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, h->family, stream);
     HIPCHK(hipGetLastError());
     if (phase_ms) {
         HIPCHK(hipEventRecord(ev[3], (hipStream_t)stream));
@@ -167,15 +169,15 @@ static void product_noalloc(const hh_handle* h, const void* x, void* y, int64_t 
     d.part = reinterpret_cast<double*>(base + bx + bt);
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (R == 1) {
-        launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->has_cont, stream);
+        launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->family, stream);
         launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(),
-                     h->has_cont, stream);
+                     h->family, stream);
     } else {
         if (R <= PANEL_MAX_R && !h->has_cont)
-            launch_dot(d, nullptr, S.d_dotp, (int64_t)S.dotp.size(), R, h->has_cont, stream);
+            launch_dot(d, nullptr, S.d_dotp, (int64_t)S.dotp.size(), R, h->family, stream);
         else
-            launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->has_cont, stream);
-        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, h->has_cont, stream);
+            launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->family, stream);
+        launch_accumulate(d, nullptr, S.d_leaf, (int64_t)S.leaf.size(), R, h->family, stream);
     }
     HIPCHK(hipGetLastError());
 }
@@ -214,6 +216,7 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
     int dev = -1;
     HIPCHK(hipGetDevice(&dev));
     std::vector<Desc> descs(count);
+    int fam = FAM_FIX;                       // q43 kernels also serve fixed-format handles
     for (int t = 0; t < count; ++t) {
         hh_handle* h = const_cast<hh_handle*>(hs[t]);
         if (!h) fail(HH_EINVAL, "a handle in the batch is NULL");
@@ -221,6 +224,7 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
         if (h->opt.io_dtype != io) fail(HH_EINVAL, "handles of a batch must share io_dtype");
         if (h->has_cont != hs[0]->has_cont)
             fail(HH_ENOTSUP, "a batch cannot mix continuum-stored and fixed-format handles");
+        fam = std::max(fam, h->family);
         check_device(h);
         for (int u = 0; u < t; ++u)
             if (hs[u] == h) fail(HH_EINVAL, "a handle appears twice in the batch (shared workspace)");
@@ -279,12 +283,11 @@ static void product_batch(const hh_handle* const* hs, int count, const void* con
                           (hipStream_t)stream));
     const int R = (int)nrhs;
     launch_gather(descs[0], bp->d_desc, count, bp->max_np, R, stream);
-    const bool cont = hs[0]->has_cont;
-    launch_dot(descs[0], bp->d_desc, bp->d_dot, bp->ndot, R, cont, stream);
+    launch_dot(descs[0], bp->d_desc, bp->d_dot, bp->ndot, R, fam, stream);
     if (R == 1)
-        launch_units(descs[0], bp->d_desc, bp->d_unit, bp->nunit, bp->d_fin, bp->nfin, cont, stream);
+        launch_units(descs[0], bp->d_desc, bp->d_unit, bp->nunit, bp->d_fin, bp->nfin, fam, stream);
     else
-        launch_accumulate(descs[0], bp->d_desc, bp->d_leaf, bp->nleaf, R, cont, stream);
+        launch_accumulate(descs[0], bp->d_desc, bp->d_leaf, bp->nleaf, R, fam, stream);
     HIPCHK(hipGetLastError());
 }
 
@@ -300,7 +303,7 @@ static double block_words(const BlockRec& r) {
     const double m = (double)(r.b.ie - r.b.ib), n = (double)(r.b.je - r.b.jb);
     if (!r.lowrank) return m * n;
     const double bits = r.fmt == HH_FMT_FP64 ? 64.0 : r.fmt == HH_FMT_FP32 ? 32.0
-                      : r.fmt == HH_FMT_CONT ? 9.0 + r.t : 16.0;
+                      : r.fmt == HH_FMT_CONT ? 9.0 + r.t : r.fmt == HH_FMT_Q43 ? 8.0 : 16.0;
     return (double)r.rank * (m + n) * bits / 64.0;
 }
 
@@ -411,6 +414,7 @@ static double decode(const void* base, int fmt, int64_t i) {
         case HH_FMT_FP64: return static_cast<const double*>(base)[i];
         case HH_FMT_FP32: return static_cast<const float*>(base)[i];
         case HH_FMT_FP16: return f16_to_f64(static_cast<const uint16_t*>(base)[i]);
+        case HH_FMT_Q43: return q43_to_f64(static_cast<const uint8_t*>(base)[i]);
         default: return bf16_to_f64(static_cast<const uint16_t*>(base)[i]);
     }
 }
@@ -694,7 +698,8 @@ void hh_plan_free(hh_plan* p) { delete p; }
 hh_status hh_quantize(const double* in, int64_t n, int format, int e, double* out) {
     GUARD_BEGIN
     if (n < 0 || (n > 0 && (!in || !out))) fail(HH_EINVAL, "bad arrays");
-    if (format < HH_FMT_FP64 || format > HH_FMT_BF16) fail(HH_EINVAL, "unknown format");
+    if (format < HH_FMT_FP64 || format > HH_FMT_Q43 || format == HH_FMT_CONT)
+        fail(HH_EINVAL, "unknown format");
     const double s = std::ldexp(1.0, -e), b = std::ldexp(1.0, e);
     for (int64_t i = 0; i < n; ++i) {
         double v = in[i] * s, q;
@@ -702,6 +707,7 @@ hh_status hh_quantize(const double* in, int64_t n, int format, int e, double* ou
             case HH_FMT_FP64: q = v; break;
             case HH_FMT_FP32: q = (double)(float)v; break;
             case HH_FMT_FP16: q = f16_to_f64(f64_to_f16_rne(v)); break;
+            case HH_FMT_Q43: q = q43_to_f64(f64_to_q43_rne(v)); break;
             default: q = bf16_to_f64(f64_to_bf16_rne(v)); break;
         }
         out[i] = q * b;

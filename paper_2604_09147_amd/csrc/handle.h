@@ -75,5 +75,6 @@ struct hh_handle {
     // fp64 factors kept when every low-rank block is stored in fp64
     bool all_fp64 = false;
     bool has_cont = false;            // some block stored in the continuum format
+    int family = 0;                   // FAM_*: the product kernels' storage family
     hh_stats stats{};
 };

@@ -129,6 +129,8 @@ __host__ __device__ uint16_t f64_to_f16_rne(double x);
 __host__ __device__ uint16_t f64_to_bf16_rne(double x);
 __host__ __device__ double f16_to_f64(uint16_t h);
 __host__ __device__ double bf16_to_f64(uint16_t b);
+__host__ __device__ uint8_t f64_to_q43_rne(double x);
+__host__ __device__ double q43_to_f64(uint8_t c);
 __host__ __device__ uint32_t f64_to_cont_rne(double x, int t);
 __host__ __device__ double cont_to_f64(uint32_t code, int t);
 

@@ -45,10 +45,21 @@ void box_coords(int64_t box, int level, int d, int64_t* c);
 // that a wave lane owning 4 consecutive rows always reads aligned vectors.
 constexpr int ROW_PAD = 4;
 
-// Storage formats of the low-rank factors: HH_FMT_FP64 .. HH_FMT_BF16 and the
+// Storage formats of the low-rank factors: HH_FMT_FP64 .. HH_FMT_BF16, the
 // continuum format HH_FMT_CONT (per block t fraction bits, 9 + t bits per
-// entry, entries packed back to back in every column).
+// entry, entries packed back to back in every column) and the 8-bit
+// HH_FMT_Q43 (NFMT_CODES format codes). A handle stores continuum or q43
+// blocks, never both, so the run lists keep NFMT slots per cluster and q43
+// runs take the continuum slot.
+constexpr int NFMT_CODES = 6;
 constexpr int NFMT = 5;
+constexpr int fmt_slot(int fmt) { return fmt == HH_FMT_Q43 ? HH_FMT_CONT : fmt; }
+// q43 codes are widened in the product kernels by moving their bits into an
+// fp16 (sign to bit 15, exponent field E to bits 10..14, fraction f to bits
+// 7..9): an fp16 has 8 more exponent bias than q43, so its value is the q43
+// value times 2^-8 for every code, subnormals included. The two factors of a
+// block thus carry 2^-16, which the block's coefficient scale takes back.
+constexpr int fmt_exp_bias(int fmt) { return fmt == HH_FMT_Q43 ? 16 : 0; }
 // Bytes of one continuum column of P entries of w bits: whole 16-byte units,
 // so every column starts 16-byte aligned (constexpr: usable in device code).
 constexpr int64_t cont_col_bytes(int64_t P, int w) {
@@ -125,7 +136,7 @@ struct LeafTask {
 // A slice of one leaf's runs (one wave of the single-vector accumulation).
 // Its runs in the unit run list are grouped by format: fp64 [rb, fe[0]),
 // fp32 [fe[0], fe[1]), fp16 [fe[1], fe[2]), bf16 [fe[2], fe[3]), continuum
-// [fe[3], fe[4]). The wave writes its partial sum of the leaf's rows to
+// or q43 [fe[3], fe[4]). The wave writes its partial sum of the leaf's rows to
 // part[po .. po + P).
 struct UnitTask {
     int64_t poff;            // padded offset of the leaf
@@ -173,15 +184,19 @@ constexpr int DOTM_MT = 1;
 constexpr int DOTP_MT = 4;
 constexpr int PANEL_MAX_R = 16;
 
-// Kernel launch wrappers (defined in the .hip files). cont: the handle (or
-// some handle of the batch) stores continuum blocks.
+// Storage family of a launch (the kernel variant): the fixed formats, the
+// continuum format with fp64, or the fixed formats with q43.
+enum { FAM_FIX = 0, FAM_CONT = 1, FAM_Q43 = 2 };
+
+// Kernel launch wrappers (defined in the .hip files). fam: the storage family
+// of the handle (of every handle of a batch).
 void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int R, void* stream);
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
-                int R, bool cont, void* stream);
+                int R, int fam, void* stream);
 void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
-                       int R, bool cont, void* stream);
+                       int R, int fam, void* stream);
 void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,
-                  const FinishTask* fin, int64_t nfin, bool cont, void* stream);
+                  const FinishTask* fin, int64_t nfin, int fam, void* stream);
 
 }  // namespace hh
 

@@ -64,6 +64,41 @@ __host__ __device__ uint16_t f64_to_bf16_rne(double x) {
     return sign | (uint16_t)out;
 }
 
+// q43 (the 8-bit row of Table tab:precisions): sign, 4 exponent bits with
+// bias 7, 3 fraction bits; normal exponents -6..7, gradual underflow below
+// 2^-6 (spacing 2^-9), largest finite value 240; the same bit patterns as OCP
+// fp8 e4m3 below 256. RNE straight from fp64. Magnitudes that round beyond
+// 240 saturate to it (factors are scaled so that their largest entry lies in
+// [64, 128), so none does).
+__host__ __device__ uint8_t f64_to_q43_rne(double x) {
+    const uint64_t bits = __builtin_bit_cast(uint64_t, x);
+    const uint8_t sign = (uint8_t)((bits >> 56) & 0x80u);
+    const int ex = (int)((bits >> 52) & 0x7FF);
+    const uint64_t man = bits & ((1ull << 52) - 1);
+    if (ex == 0x7FF) return sign | 0x77u;
+    if (ex == 0) return sign;
+    const int e = ex - 1023;
+    if (e > 8) return sign | 0x77u;
+    const uint64_t M = man | (1ull << 52);          // value = M 2^(e - 52)
+    const int ue = (e > -6 ? e : -6) - 3;           // exponent of the spacing
+    const int shift = 52 + ue - e;                  // >= 49
+    if (shift >= 64) return sign;
+    uint64_t q = M >> shift;
+    const uint64_t rem = M & ((1ull << shift) - 1);
+    const uint64_t half = 1ull << (shift - 1);
+    if (rem > half || (rem == half && (q & 1))) ++q;
+    // normal: q in [8, 16] times 2^(e - 3); a carry to 16 moves to the next binade
+    uint32_t out = e >= -6 ? (uint32_t)((e + 7) << 3) + (uint32_t)q - 8u : (uint32_t)q;
+    if (out > 0x77u) out = 0x77u;
+    return sign | (uint8_t)out;
+}
+
+__host__ __device__ double q43_to_f64(uint8_t c) {
+    const int field = (c >> 3) & 15, frac = c & 7;
+    const double v = field ? std::ldexp((double)(8 + frac), field - 10) : std::ldexp((double)frac, -9);
+    return (c & 0x80u) ? -v : v;
+}
+
 // Continuum storage: t fraction bits (7 <= t <= 23) behind an 8-bit exponent
 // with the exponent range of fp32 (gradual underflow below 2^-126), sign
 // first: a (9 + t)-bit code equal to the top 9 + t bits of the fp32 encoding of
@@ -1118,6 +1153,7 @@ __global__ void pack_kernel(const PackItem* items) {
             case HH_FMT_FP64: ((double*)it.dst)[i] = v; break;
             case HH_FMT_FP32: ((float*)it.dst)[i] = (float)v; break;
             case HH_FMT_FP16: ((uint16_t*)it.dst)[i] = f64_to_f16_rne(v); break;
+            case HH_FMT_Q43: ((uint8_t*)it.dst)[i] = f64_to_q43_rne(v); break;
             default: ((uint16_t*)it.dst)[i] = f64_to_bf16_rne(v); break;
         }
     }

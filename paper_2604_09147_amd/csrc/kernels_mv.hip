@@ -74,11 +74,13 @@ template <> struct Raw4<HH_FMT_FP64> { dbl2_t a, b; };
 template <> struct Raw4<HH_FMT_FP32> { flt4_t a; };
 template <> struct Raw4<HH_FMT_FP16> { half4_t a; };
 template <> struct Raw4<HH_FMT_BF16> { u32x2_t a; };
+template <> struct Raw4<HH_FMT_Q43> { uint32_t a; };
 
 template <int FMT>
 __device__ inline const void* elem_ptr(const void* base, int64_t i) {
     if constexpr (FMT == HH_FMT_FP64) return static_cast<const double*>(base) + i;
     else if constexpr (FMT == HH_FMT_FP32) return static_cast<const float*>(base) + i;
+    else if constexpr (FMT == HH_FMT_Q43) return static_cast<const uint8_t*>(base) + i;
     else return static_cast<const uint16_t*>(base) + i;
 }
 
@@ -103,6 +105,8 @@ __device__ inline Raw4<FMT> load4(const void* base, int64_t i) {
         r.a = NT ? ldg_nt<flt4_t>(p) : ldg<flt4_t>(p);
     } else if constexpr (FMT == HH_FMT_FP16) {
         r.a = NT ? ldg_nt<half4_t>(p) : ldg<half4_t>(p);
+    } else if constexpr (FMT == HH_FMT_Q43) {
+        r.a = NT ? ldg_nt<uint32_t>(p) : ldg<uint32_t>(p);
     } else {
         r.a = NT ? ldg_nt<u32x2_t>(p) : ldg<u32x2_t>(p);
     }
@@ -141,6 +145,8 @@ __device__ inline Raw4<FMT> bload4(rsrc_t rs, uint32_t off) {
         r.a = __builtin_bit_cast(flt4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, CP));
     } else if constexpr (FMT == HH_FMT_FP16) {
         r.a = __builtin_bit_cast(half4_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, CP));
+    } else if constexpr (FMT == HH_FMT_Q43) {
+        r.a = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, CP);
     } else {
         r.a = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, CP));
     }
@@ -149,13 +155,20 @@ __device__ inline Raw4<FMT> bload4(rsrc_t rs, uint32_t off) {
 
 template <int FMT>
 constexpr int elem_bytes() {
-    return FMT == HH_FMT_FP64 ? 8 : FMT == HH_FMT_FP32 ? 4 : 2;
+    return FMT == HH_FMT_FP64 ? 8 : FMT == HH_FMT_FP32 ? 4 : FMT == HH_FMT_Q43 ? 1 : 2;
+}
+
+// Two q43 codes, at bits 8..15 and 24..31 of t, as two fp16 (low, high half):
+// sign to bit 15, exponent field and fraction to bits 7..14, which is the
+// code's value times 2^-8 (exact, subnormals included).
+__device__ inline uint32_t q43_pair_to_h16(uint32_t t) {
+    return ((t >> 1) & 0x3F803F80u) | (t & 0x80008000u);
 }
 
 __device__ inline float bf16lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ inline float bf16hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
-// Exact widening to T (float for 16-bit formats, double otherwise).
+// Exact widening to T (float for the 16- and 8-bit formats, double otherwise).
 template <int FMT, typename T>
 __device__ inline void widen4(const Raw4<FMT>& r, T v[4]) {
     if constexpr (FMT == HH_FMT_FP64) {
@@ -164,6 +177,12 @@ __device__ inline void widen4(const Raw4<FMT>& r, T v[4]) {
         v[0] = r.a.x; v[1] = r.a.y; v[2] = r.a.z; v[3] = r.a.w;
     } else if constexpr (FMT == HH_FMT_FP16) {
         v[0] = (float)r.a.x; v[1] = (float)r.a.y; v[2] = (float)r.a.z; v[3] = (float)r.a.w;
+    } else if constexpr (FMT == HH_FMT_Q43) {
+        // 2^-8 times the stored values (the block's coefficient carries 2^16)
+        const uint32_t lo = q43_pair_to_h16(((r.a << 8) & 0x0000FF00u) | ((r.a << 16) & 0xFF000000u));
+        const uint32_t hi = q43_pair_to_h16(((r.a >> 8) & 0x0000FF00u) | (r.a & 0xFF000000u));
+        const half4_t h = __builtin_bit_cast(half4_t, u32x2_t{lo, hi});
+        v[0] = (float)h.x; v[1] = (float)h.y; v[2] = (float)h.z; v[3] = (float)h.w;
     } else {
         v[0] = bf16lo(r.a.x); v[1] = bf16hi(r.a.x); v[2] = bf16lo(r.a.y); v[3] = bf16hi(r.a.y);
     }
@@ -452,11 +471,12 @@ struct DotCont {
     }
 };
 
-// CONT: the variant for handles with continuum storage, whose low-rank blocks
-// are continuum or fp64 (a launch never mixes them with the 32- and 16-bit
-// formats); the other keeps only the fixed formats, so neither pays the
-// other's registers.
-template <int NU, int XL, bool CONT>
+// FAM (FAM_FIX, FAM_CONT, FAM_Q43): the storage family of the launch. Handles
+// with continuum storage hold continuum or fp64 low-rank blocks (a launch never
+// mixes them with the 32- and 16-bit formats); q43 comes with the fixed
+// formats. Each variant keeps only its own formats, so none pays the others'
+// registers.
+template <int NU, int XL, int FAM>
 __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks) {
     __shared__ double xs[XL];
     const DotTask t = ldrec<DotTask>(tasks + blockIdx.x);
@@ -468,10 +488,16 @@ __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks
         for (int i = threadIdx.x; i < t.P; i += 256) xs[i] = ldg<double>(x + i);
         __syncthreads();
     }
-    if constexpr (CONT) {
+    if constexpr (FAM == FAM_CONT) {
         if (t.fmt == HH_FMT_CONT) with_width(t.w, DotCont{t, x, xs, lds, D.tb, wave, lane});
         else dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane);
     } else {
+        if constexpr (FAM == FAM_Q43) {
+            if (t.fmt == HH_FMT_Q43) {
+                dot_r1_any<HH_FMT_Q43, NU>(t, x, xs, lds, D.tb, wave, lane);
+                return;
+            }
+        }
         switch (t.fmt) {
             case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane); break;
             case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32, NU>(t, x, xs, lds, D.tb, wave, lane); break;
@@ -481,13 +507,14 @@ __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks
     }
 }
 
-#define HH_DOT1_KERNEL(NAME, NU, XL, W, CONT)                                                   \
+#define HH_DOT1_KERNEL(NAME, NU, XL, W, FAM)                                                    \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void NAME(         \
         Desc d, const Desc* descs, const DotTask* tasks) {                                      \
-        dot1_body<NU, XL, CONT>(d, descs, tasks);                                               \
+        dot1_body<NU, XL, FAM>(d, descs, tasks);                                                \
     }
-HH_DOT1_KERNEL(dot1_kernel, 8, 4096, 4, false)
-HH_DOT1_KERNEL(dot1c_kernel, 8, 4096, 4, true)
+HH_DOT1_KERNEL(dot1_kernel, 8, 4096, 4, FAM_FIX)
+HH_DOT1_KERNEL(dot1c_kernel, 8, 4096, 4, FAM_CONT)
+HH_DOT1_KERNEL(dot1q_kernel, 8, 4096, 4, FAM_Q43)
 
 // -------------------------------------------------------------- accumulate
 // Apply one run to a lane's 4 rows: acc += 2^e sum_c col_c[rows] coef_c
@@ -726,21 +753,23 @@ __device__ inline void unit_runs_cont(const Desc& D, const UnitTask& ut, int b, 
     }
 }
 
-template <bool SPLIT, int UB, bool CONT>
+template <bool SPLIT, int UB, int FAM>
 __device__ inline void unit_runs(const Desc& D, const UnitTask& ut, int64_t row, int g, int G,
                                  double acc[4][1], bool pipe) {
     unit_runs_fmt<HH_FMT_FP64, SPLIT, UB>(D, ut, ut.rb, ut.fe[0], row, g, G, acc, pipe);
-    if constexpr (CONT) {
+    if constexpr (FAM == FAM_CONT) {
         unit_runs_cont<SPLIT>(D, ut, ut.fe[3], ut.fe[4], row, g, G, acc);
     } else {
         unit_runs_fmt<HH_FMT_FP32, SPLIT, UB>(D, ut, ut.fe[0], ut.fe[1], row, g, G, acc, pipe);
         unit_runs_fmt<HH_FMT_FP16, SPLIT, UB>(D, ut, ut.fe[1], ut.fe[2], row, g, G, acc, pipe);
         unit_runs_fmt<HH_FMT_BF16, SPLIT, UB>(D, ut, ut.fe[2], ut.fe[3], row, g, G, acc, pipe);
+        if constexpr (FAM == FAM_Q43)
+            unit_runs_fmt<HH_FMT_Q43, SPLIT, UB>(D, ut, ut.fe[3], ut.fe[4], row, g, G, acc, pipe);
     }
 }
 
 // Four units per workgroup, one per wave; the waves never synchronise.
-template <int UB, bool PIPE, bool CONT>
+template <int UB, bool PIPE, int FAM>
 __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int64_t ui = (int64_t)blockIdx.x * 4 + wave;
@@ -761,8 +790,8 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
         const int prow = jlo + 4 * sl;
         const int64_t row = prow < P ? prow : 0;     // clamped: in bounds, never written
         double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
-        if (G == 1) unit_runs<false, UB, CONT>(D, ut, row, 0, 1, acc, PIPE);
-        else unit_runs<true, UB, CONT>(D, ut, row, g, G, acc, PIPE);
+        if (G == 1) unit_runs<false, UB, FAM>(D, ut, row, 0, 1, acc, PIPE);
+        else unit_runs<true, UB, FAM>(D, ut, row, g, G, acc, PIPE);
         for (int off = lps; off < 64; off <<= 1)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q][0] += __shfl_xor(acc[q][0], off, 64);
@@ -774,13 +803,14 @@ __device__ inline void unit_body(Desc d, const Desc* descs, const UnitTask* unit
     }
 }
 
-#define HH_UNIT_KERNEL(NAME, UB, W, PIPE, CONT)                                              \
+#define HH_UNIT_KERNEL(NAME, UB, W, PIPE, FAM)                                               \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void NAME(         \
         Desc d, const Desc* descs, const UnitTask* units, int64_t nunits) {                    \
-        unit_body<UB, PIPE, CONT>(d, descs, units, nunits);                                     \
+        unit_body<UB, PIPE, FAM>(d, descs, units, nunits);                                      \
     }
-HH_UNIT_KERNEL(unit_kernel, 16, 4, true, false)
-HH_UNIT_KERNEL(unitc_kernel, 16, 4, true, true)
+HH_UNIT_KERNEL(unit_kernel, 16, 4, true, FAM_FIX)
+HH_UNIT_KERNEL(unitc_kernel, 16, 4, true, FAM_CONT)
+HH_UNIT_KERNEL(unitq_kernel, 16, 4, true, FAM_Q43)
 
 // y rows of one leaf: its units' partials in unit order, written in caller
 // order. Lane l owns rows 4l..4l+3 of each 256-row strip.
@@ -997,9 +1027,10 @@ struct DotmCont {
 
 // Tiles x right-hand-side groups, four per workgroup (one per wave); the groups
 // of one tile are neighbours, so its columns are read from HBM about once.
-template <int NT, bool CONT, int MT>
+template <int NT, int FAM, int MT>
 __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, const DotTask* tiles,
                                                    int64_t ntiles, int R, int ngroups) {
+    constexpr bool CONT = FAM == FAM_CONT;
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int64_t item = (int64_t)blockIdx.x * 4 + wave;
     if (item >= ntiles * ngroups) return;
@@ -1010,6 +1041,12 @@ __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, co
     if (CONT && t.fmt == HH_FMT_CONT) {
         if constexpr (CONT) with_width(t.w, DotmCont<NT, MT>{t, D, R, g, lane});
         return;
+    }
+    if constexpr (FAM == FAM_Q43) {
+        if (t.fmt == HH_FMT_Q43) {
+            dotm_tile<HH_FMT_Q43, NT, MT>(t, D, R, g, lane);
+            return;
+        }
     }
     switch (t.fmt) {
         case HH_FMT_FP64: dotm_tile<HH_FMT_FP64, NT, MT>(t, D, R, g, lane); break;
@@ -1022,7 +1059,8 @@ __global__ __launch_bounds__(256) void dotm_kernel(Desc d, const Desc* descs, co
 // Phase U for 64 rows of a leaf (four 16-row subtiles q: rows base + 4 i + q)
 // and NT tiles of right-hand sides: lane (i, k) loads rows base + 4i .. + 3 of
 // column c + k, one row per subtile; K step = 4 columns, four steps per pass.
-template <int F, int NT>
+// SLOT: the format's slot in the cluster's run list.
+template <int F, int NT, int SLOT = F>
 __device__ inline void accm_runs(const Desc& D, int64_t ci, const LeafTask& lt, int rowbase, int R,
                                  int g, int lane, dbl4_t acc[4][NT]) {
     constexpr uint32_t es = elem_bytes<F>();
@@ -1035,7 +1073,7 @@ __device__ inline void accm_runs(const Desc& D, int64_t ci, const LeafTask& lt, 
         const int r = 16 * (g * NT + u) + i;
         rr[u] = r < R ? r : R - 1;
     }
-    const int rb = ldc<int32_t>(D.cl_run + NFMT * ci + F), re = ldc<int32_t>(D.cl_run + NFMT * ci + F + 1);
+    const int rb = ldc<int32_t>(D.cl_run + NFMT * ci + SLOT), re = ldc<int32_t>(D.cl_run + NFMT * ci + SLOT + 1);
     for (int ri = rb; ri < re; ++ri) {
         const Run rn = ldrec<Run>(D.runs + ri);
         const double* coef = rn.from_x ? D.xt : D.tb;
@@ -1131,7 +1169,7 @@ __device__ inline void accm_runs_cont(const Desc& D, int64_t ci, const LeafTask&
 
 // One workgroup per (leaf, right-hand-side group); wave w owns rows 64 w ..
 // 64 w + 63 of each 256-row strip of the leaf; writes y in caller order.
-template <int NT, bool CONT>
+template <int NT, int FAM>
 __global__ __launch_bounds__(256) void accm_kernel(Desc d, const Desc* descs, const LeafTask* leaves,
                                                    int R, int ngroups) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -1154,7 +1192,9 @@ __global__ __launch_bounds__(256) void accm_kernel(Desc d, const Desc* descs, co
             accm_runs<HH_FMT_FP32, NT>(D, ci, lt, rowbase, R, g, lane, acc);
             accm_runs<HH_FMT_FP16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
             accm_runs<HH_FMT_BF16, NT>(D, ci, lt, rowbase, R, g, lane, acc);
-            if constexpr (CONT) accm_runs_cont<NT>(D, ci, lt, rowbase, R, g, lane, acc);
+            if constexpr (FAM == FAM_CONT) accm_runs_cont<NT>(D, ci, lt, rowbase, R, g, lane, acc);
+            if constexpr (FAM == FAM_Q43)
+                accm_runs<HH_FMT_Q43, NT, HH_FMT_CONT>(D, ci, lt, rowbase, R, g, lane, acc);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -1190,32 +1230,35 @@ void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int
                        descs, R);
 }
 
-template <bool CONT>
+template <int FAM>
 static void launch_dotm(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
                         int R, void* stream) {
     const int nt = rhs_tiles_per_group(R);
     const int ngroups = ((R + 15) / 16 + nt - 1) / nt;
     const unsigned grid = (unsigned)((ntasks * ngroups + 3) / 4);
-    if (!CONT && R <= PANEL_MAX_R)
-        hipLaunchKernelGGL((dotm_kernel<1, false, DOTP_MT>), dim3(grid), dim3(256), 0,
-                           (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
+    if (FAM != FAM_CONT && R <= PANEL_MAX_R)
+        hipLaunchKernelGGL((dotm_kernel<1, FAM == FAM_CONT ? FAM_FIX : FAM, DOTP_MT>), dim3(grid),
+                           dim3(256), 0, (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
     else if (nt == 1)
-        hipLaunchKernelGGL((dotm_kernel<1, CONT, DOTM_MT>), dim3(grid), dim3(256), 0,
+        hipLaunchKernelGGL((dotm_kernel<1, FAM, DOTM_MT>), dim3(grid), dim3(256), 0,
                            (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
     else if (nt == 2)
-        hipLaunchKernelGGL((dotm_kernel<2, CONT, DOTM_MT>), dim3(grid), dim3(256), 0,
+        hipLaunchKernelGGL((dotm_kernel<2, FAM, DOTM_MT>), dim3(grid), dim3(256), 0,
                            (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
     else
-        hipLaunchKernelGGL((dotm_kernel<4, CONT, DOTM_MT>), dim3(grid), dim3(256), 0,
+        hipLaunchKernelGGL((dotm_kernel<4, FAM, DOTM_MT>), dim3(grid), dim3(256), 0,
                            (hipStream_t)stream, d, descs, tasks, ntasks, R, ngroups);
 }
 
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks, int R,
-                bool cont, void* stream) {
+                int fam, void* stream) {
     if (ntasks <= 0) return;
     if (R == 1) {
-        if (cont)
+        if (fam == FAM_CONT)
             hipLaunchKernelGGL(dot1c_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
+                               d, descs, tasks);
+        else if (fam == FAM_Q43)
+            hipLaunchKernelGGL(dot1q_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
                                d, descs, tasks);
         else
             hipLaunchKernelGGL(dot1_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream,
@@ -1223,41 +1266,47 @@ void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t 
         return;
     }
     // several right-hand sides: panel tiles (up to PANEL_MAX_R right-hand
-    // sides, fixed formats only), else tiles of at most 16 columns
-    if (cont) launch_dotm<true>(d, descs, tasks, ntasks, R, stream);
-    else launch_dotm<false>(d, descs, tasks, ntasks, R, stream);
+    // sides, no continuum blocks), else tiles of at most 16 columns
+    if (fam == FAM_CONT) launch_dotm<FAM_CONT>(d, descs, tasks, ntasks, R, stream);
+    else if (fam == FAM_Q43) launch_dotm<FAM_Q43>(d, descs, tasks, ntasks, R, stream);
+    else launch_dotm<FAM_FIX>(d, descs, tasks, ntasks, R, stream);
 }
 
-template <bool CONT>
+template <int FAM>
 static void launch_accm(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
                         int R, void* stream) {
     const int nt = rhs_tiles_per_group_u(R);
     const int ngroups = ((R + 15) / 16 + nt - 1) / nt;
     const unsigned grid = (unsigned)(nleaves * ngroups);
     if (nt == 1)
-        hipLaunchKernelGGL((accm_kernel<1, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+        hipLaunchKernelGGL((accm_kernel<1, FAM>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
                            descs, leaves, R, ngroups);
     else
-        hipLaunchKernelGGL((accm_kernel<2, CONT>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
+        hipLaunchKernelGGL((accm_kernel<2, FAM>), dim3(grid), dim3(256), 0, (hipStream_t)stream, d,
                            descs, leaves, R, ngroups);
 }
 
 void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
-                       int R, bool cont, void* stream) {
+                       int R, int fam, void* stream) {
     if (nleaves <= 0) return;
-    if (cont) launch_accm<true>(d, descs, leaves, nleaves, R, stream);
-    else launch_accm<false>(d, descs, leaves, nleaves, R, stream);
+    if (fam == FAM_CONT) launch_accm<FAM_CONT>(d, descs, leaves, nleaves, R, stream);
+    else if (fam == FAM_Q43) launch_accm<FAM_Q43>(d, descs, leaves, nleaves, R, stream);
+    else launch_accm<FAM_FIX>(d, descs, leaves, nleaves, R, stream);
 }
 
 void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,
-                  const FinishTask* fin, int64_t nfin, bool cont, void* stream) {
+                  const FinishTask* fin, int64_t nfin, int fam, void* stream) {
     if (nunits > 0) {
-        if (cont)
-            hipLaunchKernelGGL(unitc_kernel, dim3((unsigned)((nunits + 3) / 4)), dim3(256), 0,
-                               (hipStream_t)stream, d, descs, units, nunits);
+        const dim3 grid((unsigned)((nunits + 3) / 4));
+        if (fam == FAM_CONT)
+            hipLaunchKernelGGL(unitc_kernel, grid, dim3(256), 0, (hipStream_t)stream, d, descs, units,
+                               nunits);
+        else if (fam == FAM_Q43)
+            hipLaunchKernelGGL(unitq_kernel, grid, dim3(256), 0, (hipStream_t)stream, d, descs, units,
+                               nunits);
         else
-            hipLaunchKernelGGL(unit_kernel, dim3((unsigned)((nunits + 3) / 4)), dim3(256), 0,
-                               (hipStream_t)stream, d, descs, units, nunits);
+            hipLaunchKernelGGL(unit_kernel, grid, dim3(256), 0, (hipStream_t)stream, d, descs, units,
+                               nunits);
     }
     if (nfin > 0)
         hipLaunchKernelGGL(finish_kernel, dim3((unsigned)((nfin + 3) / 4)), dim3(256), 0,

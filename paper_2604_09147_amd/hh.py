@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libhhmat.so")
 
 HH_OK, HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENOTSUP, HH_EINTERNAL = range(6)
 LOG, INV_R, INV_R2, GAUSS, MATERN, DOUBLE_LAYER = 1, 2, 3, 4, 5, 6
-FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16, FMT_CONT = 0, 1, 2, 3, 4
+FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16, FMT_CONT, FMT_Q43 = 0, 1, 2, 3, 4, 5
 IO_F64, IO_F32 = 0, 1
 BLK_FAR, BLK_NEAR, BLK_WEAK, BLK_DIAG, BLK_DENSE_NEAR = range(5)
 
@@ -51,8 +51,8 @@ class Stats(C.Structure):
     _fields_ = [("n", C.c_int32), ("d", C.c_int32), ("L", C.c_int32), ("ell", C.c_int32),
                 ("leaf_size", C.c_int32), ("max_rank", C.c_int32),
                 ("n_blocks_lowrank", C.c_int64), ("n_blocks_rank0", C.c_int64),
-                ("n_blocks_dense", C.c_int64), ("blocks_by_format", C.c_int64 * 5),
-                ("factor_bytes_by_format", C.c_int64 * 5), ("dense_bytes", C.c_int64),
+                ("n_blocks_dense", C.c_int64), ("blocks_by_format", C.c_int64 * 6),
+                ("factor_bytes_by_format", C.c_int64 * 6), ("dense_bytes", C.c_int64),
                 ("lowrank_entries", C.c_int64), ("dense_entries", C.c_int64),
                 ("total_columns", C.c_int64), ("storage_words", C.c_double),
                 ("storage_words_fp64", C.c_double), ("matvec_bytes", C.c_double),

@@ -12,6 +12,15 @@ from oracle import hh_oracle as O
 
 U64 = 2.0 ** -53
 
+# The C header's codes of the formats that the oracle numbers differently
+# (oracle: q43 = 4, continuum = 5; C: continuum = 4, q43 = 5).
+HH_FMT_CONT, HH_FMT_Q43 = 4, 5
+_GPU_CODE = {W.FMT_Q43: HH_FMT_Q43, O.FMT_CONT: HH_FMT_CONT}
+
+
+def gpu_format_code(oracle_fmt: int) -> int:
+    return _GPU_CODE.get(int(oracle_fmt), int(oracle_fmt))
+
 
 def rank_window(pmin: int, sketch: int, eps: float) -> float:
     """Relative distance of a discarded tail from eps^2 ||H_b||^2 within which
@@ -61,7 +70,7 @@ def format_tie(hm, sb) -> bool:
     if not sb.lowrank or hm.uniform:
         return False
     w = format_window(sb.rank, min(sb.blk.m, sb.blk.n), len(hm.blocks))
-    for f in (W.FMT_BF16, W.FMT_FP16, W.FMT_FP32):
+    for f in (W.FMT_Q43, W.FMT_BF16, W.FMT_FP16, W.FMT_FP32):
         if hm.mask & (1 << f):
             r = O.format_margin(sb.nb2, hm.total2, sb.blk.level, hm.d, hm.eps, f)
             if abs(r - 1.0) <= w:
@@ -82,7 +91,7 @@ def compare_structure(g, o) -> list:
     ties = []
     for q, sb in enumerate(o.blocks):
         r_ok = bl["rank"][q] == st["rank"][q]
-        f_ok = bl["format"][q] == st["fmt"][q]
+        f_ok = bl["format"][q] == gpu_format_code(st["fmt"][q])
         if r_ok and f_ok:
             continue
         if (not r_ok and rank_tie(sb, o.eps) and abs(int(bl["rank"][q]) - int(st["rank"][q])) == 1) or \
@@ -98,7 +107,7 @@ def exported_product(g, x, trans=False):
     """fp64 product with the GPU's own stored factors (exported and decoded),
     plus an elementwise bound on the kernel's deviation from it: fp16 / bf16
     blocks form their inner products in fp32 (x rounded to fp32, products and
-    lane sums of about P/64 terms in fp32), so per such block
+    lane sums of about P/64 terms in fp32; q43 blocks likewise), so per such block
     |err| <= gamma_P |A| (|B|^T |x|) with gamma_P = (P/64 + 4) 2^-24."""
     perm = g.perm()
     n = g.n
@@ -116,7 +125,7 @@ def exported_product(g, x, trans=False):
             if trans:
                 A, B, ib, ie, jb, je = B, A, jb, je, ib, ie
             yt[ib:ie] += A @ (B.T @ xt[jb:je])
-            if bl["format"][q] in (W.FMT_FP16, W.FMT_BF16):
+            if bl["format"][q] in (W.FMT_FP16, W.FMT_BF16, HH_FMT_Q43):
                 P = 4 * (-(-(je - jb) // 4)) + 64          # padded length, generous
                 gam = (P / 64.0 + 4.0) * 2.0 ** -24
                 bt[ib:ie] += gam * (np.abs(A) @ (np.abs(B).T @ np.abs(xt[jb:je])))

@@ -93,6 +93,30 @@ def test_quantize_matches_oracle_rounding():
             assert same.all(), (fmt, e, v[~same][:5], got[~same][:5], ref[~same][:5])
 
 
+def test_quantize_q43_matches_oracle_rounding():
+    # q43 (C code 5, oracle code 4): every code's midpoints with its neighbours,
+    # the subnormal range, random magnitudes; past 240 the library saturates
+    # where the oracle returns inf (stored factors are scaled to [64, 128))
+    hh = _lib_or_skip()
+    codes = np.arange(0, 0x78, dtype=np.uint8)
+    vals = np.ldexp(np.where(codes >> 3 > 0, 8.0 + (codes & 7), (codes & 7).astype(np.float64)),
+                    np.maximum(codes.astype(np.int64) >> 3, 1) - 10)
+    assert np.array_equal(O.round_q43(vals), vals)
+    mids = (vals[1:] + vals[:-1]) / 2
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(20000) * 2.0 ** rng.uniform(-14, 9, 20000)
+    v = np.concatenate([v, vals, -vals, mids, -mids, np.nextafter(mids, 0), np.nextafter(mids, 1e9),
+                        [2.0 ** -10, 3 * 2.0 ** -11, 2.0 ** -11, 247.9, 248.0, 1e6]])
+    for e in (0, -3, 7):
+        ref = np.ldexp(O.round_q43(np.ldexp(v, -e)), e)
+        ref = np.where(np.isinf(ref), np.sign(ref) * np.ldexp(240.0, e), ref)
+        got = hh.quantize(v, hh.FMT_Q43, e)
+        same = got == ref
+        assert same.all(), (e, v[~same][:5], got[~same][:5], ref[~same][:5])
+    with pytest.raises(hh.HHError):
+        hh.quantize(v[:4], hh.FMT_CONT, 0)
+
+
 def test_invalid_arguments_rejected_on_host():
     hh = _lib_or_skip()
     P = np.random.default_rng(0).random((100, 2))
@@ -118,6 +142,11 @@ def test_invalid_arguments_rejected_on_host():
                           1.0, -1, 8, None, C.byref(out))
         assert st == hh.HH_EINVAL and not out.value
         assert lib.hh_last_error()
+    # mask bit 4 is the continuum code, not a format the rule picks
+    opt = hh.Options(precision_mask=0x1F)
+    st = lib.hh_build(pts.ctypes.data_as(C.POINTER(C.c_double)), 100, 2, C.byref(k), 1e-6, 1.0, -1,
+                      8, C.byref(opt), C.byref(out))
+    assert st == hh.HH_EINVAL and not out.value and b"0x2F" in lib.hh_last_error()
     assert lib.hh_matvec(None, None, None, 1, None) == hh.HH_EINVAL
     lib.hh_free(None)
 
