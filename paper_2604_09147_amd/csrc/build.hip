@@ -68,6 +68,10 @@ static int64_t run_bytes_max() {
 }
 constexpr int64_t DOT_TASK_ELEMS = 65536;   // default elements per phase-V task
 constexpr int64_t DOT_X_LDS = 4096;        // rows of x staged in LDS by dot1_kernel
+// One right-hand side takes the panel tasks when a block's own phase-V tasks
+// average fewer stored bytes than this (low ranks: a workgroup would finish
+// after a few KB) and the panel tasks are at most half as many.
+constexpr int64_t DOT_PANEL_BELOW = 32768;
 
 void* DevMem::alloc(size_t bytes, bool zero) {
     void* p = nullptr;
@@ -1125,7 +1129,7 @@ static void ensure_part(hh_handle* h) {
 
 // Frees the device copies of a direction's task tables (before a rebuild).
 static void drop_tasks(hh_handle* h, TaskSet& S) {
-    for (void* p : {(void*)S.d_dot, (void*)S.d_dotm, (void*)S.d_dotp, (void*)S.d_pcols,
+    for (void* p : {(void*)S.d_dot, (void*)S.d_dotm, (void*)S.d_dotp, (void*)S.d_dot1p, (void*)S.d_pcols,
                     (void*)S.d_leaf, (void*)S.d_runs, (void*)S.d_cl_run, (void*)S.d_unit,
                     (void*)S.d_uruns, (void*)S.d_fin})
         if (p) h->mem.release(p);
@@ -1469,26 +1473,52 @@ static void build_tasks(hh_handle* h) {
                 t.w = r0.fmt == HH_FMT_CONT ? 9 + r0.t : 0;
                 S.dotp.push_back(t);
             }
+            // one right-hand side: about DOT_TASK_ELEMS elements per panel
+            // task, at least 16 DOTP_MT columns
+            if (r0.fmt != HH_FMT_CONT) {
+                const int64_t cpt = std::max<int64_t>(16 * DOTP_MT, DOT_TASK_ELEMS / std::max<int64_t>(Pl, 1));
+                for (int64_t c0 = 0; c0 < ncols; c0 += cpt) {
+                    DotTask t{};
+                    t.col0 = fptr(lr[g0]) + c0 * cbytes;
+                    t.xoff = xo;
+                    t.toff = m0 + c0;                // map position until the upload
+                    t.P = (int32_t)Pl;
+                    t.ncols = (int32_t)std::min<int64_t>(cpt, ncols - c0);
+                    t.fmt = r0.fmt;
+                    t.hid = 0;
+                    t.exp = 0;
+                    t.w = 0;
+                    S.dot1p.push_back(t);
+                }
+            }
             g0 = g1;
         }
     }
     // several-RHS tiles ordered by the cluster of x they read (column cluster
     // for H, row cluster for H^T), so that x_J stays in L2 across its blocks
     for (int dir = 0; dir < 2; ++dir) {
-        for (std::vector<DotTask>* v : {&(dir == 0 ? F : T).dotm, &(dir == 0 ? F : T).dotp})
+        for (std::vector<DotTask>* v : {&(dir == 0 ? F : T).dotm, &(dir == 0 ? F : T).dotp,
+                                        &(dir == 0 ? F : T).dot1p})
             std::stable_sort(v->begin(), v->end(), [](const DotTask& a, const DotTask& b) {
                 return std::make_tuple(a.P, a.xoff) < std::make_tuple(b.P, b.xoff);
             });
     }
     for (TaskSet* S : {&F, &T}) {
         S->d_pcols = upload(h->mem, S->pcols);
-        for (DotTask& t : S->dotp) {
-            t.cmap = S->d_pcols + t.toff;
-            t.toff = 0;
-        }
+        for (std::vector<DotTask>* v : {&S->dotp, &S->dot1p})
+            for (DotTask& t : *v) {
+                t.cmap = S->d_pcols + t.toff;
+                t.toff = 0;
+            }
+        double dot_bytes = 0.0;
+        for (const DotTask& t : S->dot) dot_bytes += (double)t.ncols * t.P * (double)fmt_size(t.fmt);
+        S->dot_panel = !h->has_cont && !S->dot.empty() && 2 * S->dot1p.size() <= S->dot.size() &&
+                       dot_bytes < (double)DOT_PANEL_BELOW * (double)S->dot.size();
+        if (!S->dot_panel) S->dot1p.clear();
         S->d_dot = upload(h->mem, S->dot);
         S->d_dotm = upload(h->mem, S->dotm);
         S->d_dotp = upload(h->mem, S->dotp);
+        S->d_dot1p = upload(h->mem, S->dot1p);
         S->d_leaf = upload(h->mem, S->leaf);
         S->d_runs = upload(h->mem, S->runs);
         S->d_cl_run = upload(h->mem, S->cl_run);

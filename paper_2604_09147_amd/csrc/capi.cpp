@@ -89,7 +89,9 @@ static void product(const hh_handle* hc, const void* x, void* y, int64_t nrhs, v
     }
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (phase_ms) HIPCHK(hipEventRecord(ev[1], (hipStream_t)stream));
-    if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->family, stream);
+    if (R == 1 && S.dot_panel)
+        launch_dot1_panel(d, nullptr, S.d_dot1p, (int64_t)S.dot1p.size(), h->family, stream);
+    else if (R == 1) launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->family, stream);
     else if (R <= PANEL_MAX_R && !h->has_cont)
         launch_dot(d, nullptr, S.d_dotp, (int64_t)S.dotp.size(), R, h->family, stream);
     else launch_dot(d, nullptr, S.d_dotm, (int64_t)S.dotm.size(), R, h->family, stream);
@@ -169,7 +171,10 @@ static void product_noalloc(const hh_handle* h, const void* x, void* y, int64_t 
     d.part = reinterpret_cast<double*>(base + bx + bt);
     launch_gather(d, nullptr, 1, h->np, R, stream);
     if (R == 1) {
-        launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->family, stream);
+        if (S.dot_panel)
+            launch_dot1_panel(d, nullptr, S.d_dot1p, (int64_t)S.dot1p.size(), h->family, stream);
+        else
+            launch_dot(d, nullptr, S.d_dot, (int64_t)S.dot.size(), R, h->family, stream);
         launch_units(d, nullptr, S.d_unit, (int64_t)S.unit.size(), S.d_fin, (int64_t)S.fin.size(),
                      h->family, stream);
     } else {

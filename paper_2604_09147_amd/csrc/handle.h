@@ -23,6 +23,8 @@ struct TaskSet {                      // one direction of the product
     std::vector<DotTask> dot;
     std::vector<DotTask> dotm;        // tiles of at most 16 columns (several RHS)
     std::vector<DotTask> dotp;        // panel tiles (2 .. PANEL_MAX_R right-hand sides)
+    std::vector<DotTask> dot1p;       // panel tasks of one right-hand side
+    bool dot_panel = false;           // one right-hand side runs phase V on dot1p
     std::vector<int64_t> pcols;       // their column maps (DotTask::cmap)
     std::vector<LeafTask> leaf;
     std::vector<UnitTask> unit;       // single-vector work units, leaf by leaf
@@ -33,6 +35,7 @@ struct TaskSet {                      // one direction of the product
     DotTask* d_dot = nullptr;
     DotTask* d_dotm = nullptr;
     DotTask* d_dotp = nullptr;
+    DotTask* d_dot1p = nullptr;
     int64_t* d_pcols = nullptr;
     LeafTask* d_leaf = nullptr;
     UnitTask* d_unit = nullptr;

@@ -193,6 +193,9 @@ enum { FAM_FIX = 0, FAM_CONT = 1, FAM_Q43 = 2 };
 void launch_gather(const Desc& d, const Desc* descs, int nh, int64_t max_np, int R, void* stream);
 void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
                 int R, int fam, void* stream);
+// One right-hand side over panel tasks (DotTask::cmap set); fam FAM_FIX or FAM_Q43.
+void launch_dot1_panel(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
+                       int fam, void* stream);
 void launch_accumulate(const Desc& d, const Desc* descs, const LeafTask* leaves, int64_t nleaves,
                        int R, int fam, void* stream);
 void launch_units(const Desc& d, const Desc* descs, const UnitTask* units, int64_t nunits,

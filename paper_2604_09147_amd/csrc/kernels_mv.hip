@@ -330,7 +330,9 @@ __global__ void gather_kernel(Desc d, const Desc* descs, int R) {
 // NU, eight loads of 16 bytes per lane; four of 32 bytes for fp64).
 // Units past the last column or row re-read an in-bounds element and are
 // discarded (column clamped, weight zero), so every load is unconditional.
-template <int FMT, int UR, int NU = 8>
+// PANEL: the task's columns may belong to several blocks (a panel task);
+// column c's coefficient index and exponent come from t.cmap[c].
+template <int FMT, int UR, int NU = 8, bool PANEL = false>
 __device__ void dot_r1(const DotTask& t, const double* xg, const double* xs, bool lds,
                        double* tb, int wave, int lane) {
     constexpr int UC = (FMT == HH_FMT_FP64 ? NU / 2 : NU) / UR;
@@ -375,13 +377,21 @@ __device__ void dot_r1(const DotTask& t, const double* xg, const double* xs, boo
         }
 #pragma unroll
         for (int uc = 0; uc < UC; ++uc) {
-            const double s = ldexp(wave_sum((double)a[uc]), t.exp);
-            if (lane == 0 && c0 + uc < t.ncols) stg<double>(tb + t.toff + c0 + uc, s);
+            if constexpr (PANEL) {
+                const double s = wave_sum((double)a[uc]);
+                if (lane == 0 && c0 + uc < t.ncols) {
+                    const int64_t m = ldg<int64_t>(t.cmap + c0 + uc);
+                    stg<double>(tb + (m & (((int64_t)1 << 40) - 1)), ldexp(s, (int)(m >> 40) - 1024));
+                }
+            } else {
+                const double s = ldexp(wave_sum((double)a[uc]), t.exp);
+                if (lane == 0 && c0 + uc < t.ncols) stg<double>(tb + t.toff + c0 + uc, s);
+            }
         }
     }
 }
 
-template <int FMT, int NU>
+template <int FMT, int NU, bool PANEL = false>
 __device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs, bool lds,
                            double* tb, int wave, int lane) {
     constexpr int NF = FMT == HH_FMT_FP64 ? NU / 2 : NU;   // loads of 16 bytes per lane
@@ -389,11 +399,11 @@ __device__ void dot_r1_any(const DotTask& t, const double* xg, const double* xs,
     constexpr int R2 = NF < 2 ? NF : 2, R4 = NF < 4 ? NF : 4, R8 = NF < 8 ? NF : 8;
     // x not staged in LDS (long columns): four columns per pass share each x
     // load (two for fp64)
-    if (!lds && nb > 2) dot_r1<FMT, R2, NU>(t, xg, xs, lds, tb, wave, lane);
-    else if (nb <= 1) dot_r1<FMT, 1, NU>(t, xg, xs, lds, tb, wave, lane);
-    else if (nb <= 2) dot_r1<FMT, R2, NU>(t, xg, xs, lds, tb, wave, lane);
-    else if (nb <= 4) dot_r1<FMT, R4, NU>(t, xg, xs, lds, tb, wave, lane);
-    else dot_r1<FMT, R8, NU>(t, xg, xs, lds, tb, wave, lane);
+    if (!lds && nb > 2) dot_r1<FMT, R2, NU, PANEL>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 1) dot_r1<FMT, 1, NU, PANEL>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 2) dot_r1<FMT, R2, NU, PANEL>(t, xg, xs, lds, tb, wave, lane);
+    else if (nb <= 4) dot_r1<FMT, R4, NU, PANEL>(t, xg, xs, lds, tb, wave, lane);
+    else dot_r1<FMT, R8, NU, PANEL>(t, xg, xs, lds, tb, wave, lane);
 }
 
 // Continuum columns: UC columns x UR pieces of 256 rows per wave iteration,
@@ -475,8 +485,8 @@ struct DotCont {
 // with continuum storage hold continuum or fp64 low-rank blocks (a launch never
 // mixes them with the 32- and 16-bit formats); q43 comes with the fixed
 // formats. Each variant keeps only its own formats, so none pays the others'
-// registers.
-template <int NU, int XL, int FAM>
+// registers. PANEL: panel tasks (fixed formats and q43 only).
+template <int NU, int XL, int FAM, bool PANEL = false>
 __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks) {
     __shared__ double xs[XL];
     const DotTask t = ldrec<DotTask>(tasks + blockIdx.x);
@@ -489,20 +499,21 @@ __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks
         __syncthreads();
     }
     if constexpr (FAM == FAM_CONT) {
+        static_assert(!PANEL, "no panel tasks over continuum storage");
         if (t.fmt == HH_FMT_CONT) with_width(t.w, DotCont{t, x, xs, lds, D.tb, wave, lane});
         else dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane);
     } else {
         if constexpr (FAM == FAM_Q43) {
             if (t.fmt == HH_FMT_Q43) {
-                dot_r1_any<HH_FMT_Q43, NU>(t, x, xs, lds, D.tb, wave, lane);
+                dot_r1_any<HH_FMT_Q43, NU, PANEL>(t, x, xs, lds, D.tb, wave, lane);
                 return;
             }
         }
         switch (t.fmt) {
-            case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-            case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-            case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
-            default: dot_r1_any<HH_FMT_BF16, NU>(t, x, xs, lds, D.tb, wave, lane); break;
+            case HH_FMT_FP64: dot_r1_any<HH_FMT_FP64, NU, PANEL>(t, x, xs, lds, D.tb, wave, lane); break;
+            case HH_FMT_FP32: dot_r1_any<HH_FMT_FP32, NU, PANEL>(t, x, xs, lds, D.tb, wave, lane); break;
+            case HH_FMT_FP16: dot_r1_any<HH_FMT_FP16, NU, PANEL>(t, x, xs, lds, D.tb, wave, lane); break;
+            default: dot_r1_any<HH_FMT_BF16, NU, PANEL>(t, x, xs, lds, D.tb, wave, lane); break;
         }
     }
 }
@@ -515,6 +526,17 @@ __device__ inline void dot1_body(Desc d, const Desc* descs, const DotTask* tasks
 HH_DOT1_KERNEL(dot1_kernel, 8, 4096, 4, FAM_FIX)
 HH_DOT1_KERNEL(dot1c_kernel, 8, 4096, 4, FAM_CONT)
 HH_DOT1_KERNEL(dot1q_kernel, 8, 4096, 4, FAM_Q43)
+
+// Panel tasks: the columns of consecutive blocks that share the x slice, the
+// format and the stride, one task per DOT_TASK_ELEMS-sized piece of the panel
+// (used when the blocks' own tasks would be a few KB each).
+#define HH_DOT1P_KERNEL(NAME, FAM)                                                              \
+    __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void NAME(         \
+        Desc d, const Desc* descs, const DotTask* tasks) {                                      \
+        dot1_body<8, 4096, FAM, true>(d, descs, tasks);                                         \
+    }
+HH_DOT1P_KERNEL(dot1p_kernel, FAM_FIX)
+HH_DOT1P_KERNEL(dot1pq_kernel, FAM_Q43)
 
 // -------------------------------------------------------------- accumulate
 // Apply one run to a lane's 4 rows: acc += 2^e sum_c col_c[rows] coef_c
@@ -1270,6 +1292,17 @@ void launch_dot(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t 
     if (fam == FAM_CONT) launch_dotm<FAM_CONT>(d, descs, tasks, ntasks, R, stream);
     else if (fam == FAM_Q43) launch_dotm<FAM_Q43>(d, descs, tasks, ntasks, R, stream);
     else launch_dotm<FAM_FIX>(d, descs, tasks, ntasks, R, stream);
+}
+
+void launch_dot1_panel(const Desc& d, const Desc* descs, const DotTask* tasks, int64_t ntasks,
+                       int fam, void* stream) {
+    if (ntasks <= 0) return;
+    if (fam == FAM_Q43)
+        hipLaunchKernelGGL(dot1pq_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, tasks);
+    else
+        hipLaunchKernelGGL(dot1p_kernel, dim3((unsigned)ntasks), dim3(256), 0, (hipStream_t)stream, d,
+                           descs, tasks);
 }
 
 template <int FAM>
