@@ -260,7 +260,11 @@ def _stream_ptr(stream=None, tensors=()):
 
 
 class HMatrix:
-    """An H_h matrix built on the current GPU (wraps hh_build / hh_free)."""
+    """An H_h matrix built on the current GPU (wraps hh_build / hh_free).
+
+    mask: bit f enables storage format f for the format rule (FMT_FP64,
+    FMT_FP32, FMT_FP16, FMT_BF16, FMT_Q43; 0xF = the four fixed formats),
+    as hh_options.precision_mask in include/hh.h."""
 
     def __init__(self, points, kernel: int, tol: float, eta: float, switch_level: int,
                  leaf_size: int, scale: float = 1.0, h: float = 1.0, normals=None,
