@@ -117,6 +117,20 @@ def test_quantize_q43_matches_oracle_rounding():
         hh.quantize(v[:4], hh.FMT_CONT, 0)
 
 
+def test_q43_code_read_as_fp16_is_the_value_times_2_to_the_minus_8():
+    # the product kernels widen a q43 code by moving its sign to bit 15 and its
+    # exponent and fraction to bits 7..14 of an fp16; that is exact for every
+    # code (subnormals included) once the block's scale carries 2^8 per factor
+    codes = np.arange(256, dtype=np.uint16)
+    h16 = (((codes & 0x7F) << 7) | ((codes & 0x80) << 8)).astype(np.uint16).view(np.float16)
+    e, f = (codes >> 3) & 15, codes & 7
+    val = np.ldexp(np.where(e > 0, 8.0 + f, f.astype(np.float64)), np.maximum(e.astype(np.int64), 1) - 10)
+    val = np.where(codes & 0x80, -val, val)
+    assert np.array_equal(h16.astype(np.float64) * 256.0, val)
+    finite = codes[(codes & 0x7F) <= 0x77]
+    assert np.array_equal(O.round_q43(val[finite]), val[finite])
+
+
 def test_invalid_arguments_rejected_on_host():
     hh = _lib_or_skip()
     P = np.random.default_rng(0).random((100, 2))
